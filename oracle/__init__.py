@@ -1,0 +1,207 @@
+"""ctypes shim over the plain FP64 CPU reference (dg_oracle.cpp).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline leg of the benchmark, never by the library.  The reference shares no
+source with the GPU path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "dg_oracle.cpp")
+LIB = os.path.join(HERE, "libdgoracle.so")
+
+
+def build(openmp: bool = False) -> str:
+    """Compile the reference with -O2 and no fast-math."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-o", LIB, SRC]
+    subprocess.check_call(cmd)
+    return LIB
+
+
+class OraParams(ct.Structure):
+    _fields_ = [(n, ct.c_double) for n in
+                ("g", "cvd", "cvv", "cl", "cpd", "cpv", "Rd", "Rv", "Lref", "Tref", "eref", "pref")] + \
+               [("rain", ct.c_int), ("vr_mode", ct.c_int)] + \
+               [(n, ct.c_double) for n in ("vr_const", "rho_w", "N0r", "v0r", "q_au")]
+
+
+class OraMesh(ct.Structure):
+    _fields_ = [("dim", ct.c_int), ("n", ct.c_int * 3), ("lo", ct.c_double * 3),
+                ("hi", ct.c_double * 3), ("bc", ct.c_int * 3), ("order", ct.c_int)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build()
+        L = ct.CDLL(LIB)
+        dp = ct.POINTER(ct.c_double)
+        L.ora_default_params.argtypes = [ct.POINTER(OraParams)]
+        L.ora_tables.argtypes = [ct.c_int, dp, dp, dp, dp]
+        L.ora_esat.argtypes = [ct.POINTER(OraParams), ct.c_double]
+        L.ora_esat.restype = ct.c_double
+        L.ora_rho_vs.argtypes = [ct.POINTER(OraParams), ct.c_double]
+        L.ora_rho_vs.restype = ct.c_double
+        L.ora_split.argtypes = [ct.POINTER(OraParams)] + [ct.c_double] * 4 + [dp] * 3
+        L.ora_split_jvp.argtypes = [ct.POINTER(OraParams)] + [ct.c_double] * 8 + [dp] * 4
+        L.ora_create.argtypes = [ct.POINTER(OraMesh), ct.POINTER(OraParams), ct.c_int, dp, dp, dp, dp]
+        L.ora_create.restype = ct.c_void_p
+        L.ora_destroy.argtypes = [ct.c_void_p]
+        L.ora_background_pressure.argtypes = [ct.c_void_p, dp]
+        L.ora_split_field.argtypes = [ct.c_void_p, dp, dp, dp, dp, dp, dp]
+        L.ora_rhs.argtypes = [ct.c_void_p, dp, dp, dp]
+        L.ora_rk_step.argtypes = [ct.c_void_p, dp, ct.c_double, ct.c_int, ct.c_int, dp]
+        L.ora_rhs_jvp.argtypes = [ct.c_void_p, dp, dp, dp, dp]
+        L.ora_rk_jvp.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_int, ct.c_int]
+        L.ora_mass.argtypes = [ct.c_void_p, dp, dp]
+        L.ora_point.argtypes = [ct.c_void_p, dp, ct.c_int, dp, dp, dp]
+        L.ora_face.argtypes = [ct.c_void_p, dp, ct.c_int, dp, ct.c_int, ct.c_int, dp]
+        L.ora_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_long), ct.POINTER(ct.c_int),
+                                ct.POINTER(ct.c_int)]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ct.POINTER(ct.c_double))
+
+
+def default_params(**over) -> OraParams:
+    p = OraParams()
+    lib().ora_default_params(ct.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def tables(k: int):
+    p1 = k + 1
+    x, w = np.zeros(p1), np.zeros(p1)
+    D, Dh = np.zeros((p1, p1)), np.zeros((p1, p1))
+    rc = lib().ora_tables(k, _p(x), _p(w), _p(D), _p(Dh))
+    assert rc == 0
+    return x, w, D, Dh
+
+
+def esat(P: OraParams, T: float) -> float:
+    return lib().ora_esat(ct.byref(P), T)
+
+
+def rho_vs(P: OraParams, T: float) -> float:
+    return lib().ora_rho_vs(ct.byref(P), T)
+
+
+def split(P: OraParams, rd, rm, rr, re):
+    T, rv, rc = ct.c_double(), ct.c_double(), ct.c_double()
+    it = lib().ora_split(ct.byref(P), rd, rm, rr, re, ct.byref(T), ct.byref(rv), ct.byref(rc))
+    return T.value, rv.value, rc.value, it
+
+
+def split_jvp(P: OraParams, x, dx):
+    T, dT, rv, drv = (ct.c_double() for _ in range(4))
+    rc = lib().ora_split_jvp(ct.byref(P), *x, *dx, ct.byref(T), ct.byref(dT), ct.byref(rv),
+                             ct.byref(drv))
+    assert rc == 0
+    return T.value, dT.value, rv.value, drv.value
+
+
+class Oracle:
+    """One mesh + background; all arrays float64 in the U[v][e][n] layout."""
+
+    def __init__(self, mesh, params: OraParams, nvars: int, bg: Dict[str, np.ndarray]):
+        M = OraMesh()
+        M.dim = mesh.dim
+        for a in range(mesh.dim):
+            M.n[a] = int(mesh.n[a]); M.lo[a] = float(mesh.lo[a]); M.hi[a] = float(mesh.hi[a])
+            M.bc[a] = int(mesh.bc[a])
+        M.order = mesh.order
+        self.mesh, self.P, self.nvars = mesh, params, nvars
+        self._bg = [np.ascontiguousarray(bg[k], dtype=np.float64) for k in ("rho_d", "rho_m", "rho_r", "E")]
+        self.h = lib().ora_create(ct.byref(M), ct.byref(params), nvars, *[_p(a) for a in self._bg])
+        if not self.h:
+            raise ValueError("oracle rejected the mesh/order/nvars")
+        self.shape = (nvars, mesh.ne, mesh.npe)
+
+    @classmethod
+    def for_case(cls, case, **over):
+        P = default_params(g=case.g, rain=case.rain, vr_const=case.vr_const, **over)
+        return cls(case.mesh, P, case.nvars, case.bg)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().ora_destroy(self.h)
+            self.h = None
+
+    def pbar(self) -> np.ndarray:
+        out = np.zeros(self.mesh.nzq)
+        lib().ora_background_pressure(self.h, _p(out))
+        return out
+
+    def split_field(self, U: np.ndarray):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        outs = [np.zeros(self.shape[1:]) for _ in range(5)]
+        bad = lib().ora_split_field(self.h, _p(U), *[_p(o) for o in outs])
+        return dict(T=outs[0], rho_v=outs[1], rho_c=outs[2], p_prime=outs[3], c_m=outs[4], bad=bad)
+
+    def rhs(self, U: np.ndarray):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        dU = np.zeros_like(U)
+        f = ct.c_double()
+        lib().ora_rhs(self.h, _p(U), _p(dU), ct.byref(f))
+        return dU
+
+    def rk(self, U: np.ndarray, dt: float, nsteps: int, scheme: int = 0):
+        U = np.array(U, dtype=np.float64, order="C", copy=True)
+        f = ct.c_double()
+        lib().ora_rk_step(self.h, _p(U), dt, nsteps, scheme, ct.byref(f))
+        return U, f.value
+
+    def rhs_jvp(self, U: np.ndarray, V: np.ndarray):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        dU, JV = np.zeros_like(U), np.zeros_like(U)
+        lib().ora_rhs_jvp(self.h, _p(U), _p(V), _p(dU), _p(JV))
+        return dU, JV
+
+    def rk_jvp(self, U: np.ndarray, V: np.ndarray, dt: float, nsteps: int, scheme: int = 0):
+        U = np.array(U, dtype=np.float64, order="C", copy=True)
+        V = np.array(V, dtype=np.float64, order="C", copy=True)
+        lib().ora_rk_jvp(self.h, _p(U), _p(V), dt, nsteps, scheme)
+        return U, V
+
+    def mass(self, U: np.ndarray) -> np.ndarray:
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        out = np.zeros(3)
+        lib().ora_mass(self.h, _p(U), _p(out))
+        return out
+
+    def point(self, Uq: np.ndarray, iz: int):
+        Uq = np.ascontiguousarray(Uq, dtype=np.float64)
+        d = self.mesh.dim
+        F, G, lam = np.zeros((d, self.nvars)), np.zeros(self.nvars), np.zeros(d)
+        lib().ora_point(self.h, _p(Uq), iz, _p(F), _p(G), _p(lam))
+        return F, G, lam
+
+    def face(self, Um: np.ndarray, izm: int, Up: np.ndarray, izp: int, j: int):
+        Um = np.ascontiguousarray(Um, dtype=np.float64)
+        Up = np.ascontiguousarray(Up, dtype=np.float64)
+        Fs = np.zeros(self.nvars)
+        lib().ora_face(self.h, _p(Um), izm, _p(Up), izp, j, _p(Fs))
+        return Fs
+
+    def stats(self):
+        it, mx, bad = ct.c_long(), ct.c_int(), ct.c_int()
+        lib().ora_stats(self.h, ct.byref(it), ct.byref(mx), ct.byref(bad))
+        return dict(iters_total=it.value, max_iters=mx.value, bad=bad.value)

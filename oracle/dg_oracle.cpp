@@ -1,0 +1,754 @@
+// Plain, slow FP64 reference of the moist DG right-hand side, the implicit
+// condensation split and the SSP Runge-Kutta step.
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the library or its Python binding may
+// link, import or call this file; only the tests, the smoke check and the CPU
+// baseline leg of the benchmark do.  It shares no source with the GPU path.
+//
+// Each routine follows the paper's statement of the problem in the order the
+// paper gives it:
+//   * state, pressure and energy relations .......... Section 2 (equation of
+//     state; energy-temperature relation)
+//   * saturation vapour pressure .................... Section 2.1 (Clausius-
+//     Clapeyron form with linear latent heat)
+//   * implicit condensation split ................... Section 2.2 (system for
+//     rho e, rho_v = min(e_s/(R_v T), rho_m), rho_c = rho_m - rho_v)
+//   * perturbation fluxes and sources ............... Section 2.3 (perturbation
+//     form of the moist Euler system) and Section 2.1 (Kessler sources)
+//   * DG weak form, Lax-Friedrichs flux, wave speed,
+//     slip walls ..................................... Section 3.2
+//   * diagonal mass, SSPRK(4,3) ...................... Section 3.3
+//   * pointwise reconstruction ...................... Section 3.4
+// The basis is nodal Gauss-Lobatto collocation on an affine box (nodes double
+// as quadrature points), so the L2 projection of Section 3.4 is the identity.
+//
+// The scalar type is a template parameter: `double` gives the reference
+// values, `Dual` (value + one tangent) gives exact directional derivatives of
+// the same code for the adjoint checks.  Where the method has a kink (min in
+// the split, max in the wave speed, abs, clamps at zero) the derivative of the
+// active branch is taken; ties go to the unsaturated branch, to the minus side
+// of the face, sign(0) = 0, and a clamp has derivative 0 at or below zero.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+#include <algorithm>
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// forward-mode scalar
+// ---------------------------------------------------------------------------
+struct Dual {
+  double v, d;
+  Dual() : v(0), d(0) {}
+  Dual(double a) : v(a), d(0) {}
+  Dual(double a, double b) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) { return Dual(a.v / b.v, (a.d * b.v - a.v * b.d) / (b.v * b.v)); }
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+inline Dual operator+(Dual a, double b) { return Dual(a.v + b, a.d); }
+inline Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+inline Dual operator-(Dual a, double b) { return Dual(a.v - b, a.d); }
+inline Dual operator-(double a, Dual b) { return Dual(a - b.v, -b.d); }
+inline Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+inline Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+inline Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
+inline Dual operator/(double a, Dual b) { return Dual(a / b.v, -a * b.d / (b.v * b.v)); }
+inline Dual exp(Dual a) { double e = std::exp(a.v); return Dual(e, e * a.d); }
+inline Dual log(Dual a) { return Dual(std::log(a.v), a.d / a.v); }
+inline Dual sqrt(Dual a) { double s = std::sqrt(a.v); return Dual(s, a.d / (2.0 * s)); }
+// x^p for p > 0; at x = 0 the value and the tangent are taken as 0
+inline Dual pow(Dual a, double p) {
+  if (a.v == 0.0) return Dual(0.0, 0.0);
+  double y = std::pow(a.v, p);
+  return Dual(y, p * y / a.v * a.d);
+}
+
+using std::exp;
+using std::log;
+using std::sqrt;
+
+inline double val(double a) { return a; }
+inline double val(Dual a) { return a.v; }
+inline double pw(double a, double p) { return std::pow(a, p); }
+inline Dual pw(Dual a, double p) { return pow(a, p); }
+
+template <class R> inline R absr(R a) {
+  if (val(a) > 0) return a;
+  if (val(a) < 0) return -a;
+  return R(0.0);
+}
+template <class R> inline R pos(R a) { return val(a) > 0 ? a : R(0.0); }  // max(a, 0)
+template <class R> inline R max_minus(R a, R b) { return val(a) >= val(b) ? a : b; }
+
+}  // namespace
+
+extern "C" {
+
+// Parameters of the model (thermodynamic table of the paper's appendix, g, the
+// rain closure and the split's stopping rule).
+struct OraParams {
+  double g, cvd, cvv, cl, cpd, cpv, Rd, Rv, Lref, Tref, eref, pref;
+  int rain;        // 0: no rain (nvars = 3 + d), 1: Kessler warm rain (4 + d)
+  int vr_mode;     // 0: constant v_r, 1: COSMO formula
+  double vr_const, rho_w, N0r, v0r, q_au;
+};
+
+struct OraMesh {
+  int dim;          // 2 or 3; axis dim-1 is vertical
+  int n[3];         // elements per axis
+  double lo[3], hi[3];
+  int bc[3];        // 0 periodic, 1 slip wall (on both ends of that axis)
+  int order;        // polynomial order k
+};
+
+void ora_default_params(OraParams* p) {
+  // appendix table of thermodynamic parameters
+  p->cl = 4218.0; p->cpd = 1005.0; p->cpv = 1850.0; p->cvd = 718.0; p->cvv = 1390.0;
+  p->eref = 610.7; p->Lref = 2.835e6; p->Rd = 287.05; p->Rv = 461.51; p->Tref = 273.15;
+  p->pref = 1.0e5;
+  p->g = 9.81;
+  p->rain = 0; p->vr_mode = 0; p->vr_const = 5.0;
+  // COSMO warm-rain distribution parameters (Section 2.1)
+  p->rho_w = 1000.0; p->N0r = 8.0e6; p->v0r = 130.0; p->q_au = 0.0;
+}
+
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Gauss-Lobatto tables
+// ---------------------------------------------------------------------------
+// Legendre P_k and P_k' by the three-term recurrence.
+void legendre(int k, double x, double* P, double* dP) {
+  double p0 = 1.0, p1 = x, d0 = 0.0, d1 = 1.0;
+  if (k == 0) { *P = 1.0; *dP = 0.0; return; }
+  for (int m = 1; m < k; ++m) {
+    double p2 = ((2.0 * m + 1.0) * x * p1 - m * p0) / (m + 1.0);
+    double d2 = d0 + (2.0 * m + 1.0) * p1;   // P'_{m+1} = P'_{m-1} + (2m+1) P_m
+    p0 = p1; p1 = p2; d0 = d1; d1 = d2;
+  }
+  *P = p1; *dP = d1;
+}
+
+struct Tables {
+  int k;
+  std::vector<double> x, w;   // nodes and weights on [-1, 1]
+  std::vector<double> D;      // D[a*(k+1)+i] = l_i'(x_a)
+  std::vector<double> Dhat;   // Dhat[i*(k+1)+a] = w_a D[a][i] / w_i
+};
+
+Tables make_tables(int k) {
+  Tables t;
+  t.k = k;
+  int p1 = k + 1;
+  t.x.assign(p1, 0.0); t.w.assign(p1, 0.0);
+  t.x[0] = -1.0; t.x[k] = 1.0;
+  // interior nodes: roots of P_k', Newton from Chebyshev-Lobatto guesses.
+  // (P_k')' = (2x P_k' - k(k+1) P_k)/(1 - x^2) from Legendre's equation.
+  for (int i = 1; i < k; ++i) {
+    double xx = -std::cos(M_PI * i / k);
+    for (int it = 0; it < 100; ++it) {
+      double P, dP;
+      legendre(k, xx, &P, &dP);
+      double d2P = (2.0 * xx * dP - k * (k + 1.0) * P) / (1.0 - xx * xx);
+      double dx = dP / d2P;
+      xx -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    t.x[i] = xx;
+  }
+  for (int i = 0; i < p1; ++i) {
+    double P, dP;
+    legendre(k, t.x[i], &P, &dP);
+    t.w[i] = 2.0 / (k * (k + 1.0) * P * P);
+  }
+  // differentiation matrix from barycentric weights
+  std::vector<double> lam(p1, 1.0);
+  for (int i = 0; i < p1; ++i)
+    for (int m = 0; m < p1; ++m)
+      if (m != i) lam[i] /= (t.x[i] - t.x[m]);
+  t.D.assign(p1 * p1, 0.0);
+  for (int a = 0; a < p1; ++a) {
+    double s = 0.0;
+    for (int i = 0; i < p1; ++i) {
+      if (i == a) continue;
+      double v = (lam[i] / lam[a]) / (t.x[a] - t.x[i]);
+      t.D[a * p1 + i] = v;
+      s += v;
+    }
+    t.D[a * p1 + a] = -s;
+  }
+  t.Dhat.assign(p1 * p1, 0.0);
+  for (int i = 0; i < p1; ++i)
+    for (int a = 0; a < p1; ++a) t.Dhat[i * p1 + a] = t.w[a] * t.D[a * p1 + i] / t.w[i];
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// thermodynamics (Section 2)
+// ---------------------------------------------------------------------------
+// saturation vapour pressure, Clausius-Clapeyron with linear latent heat
+template <class R> R esat(const OraParams& P, R T) {
+  double a = (P.cpv - P.cl) / P.Rv;
+  double b = (P.Lref - (P.cpv - P.cl) * P.Tref) / P.Rv;
+  return P.eref * pw(T / P.Tref, a) * exp(b * (1.0 / P.Tref - 1.0 / T));
+}
+// saturation vapour density from the vapour equation of state p_v = rho_v R_v T
+template <class R> R rho_vs(const OraParams& P, R T) { return esat(P, T) / (P.Rv * T); }
+
+double drho_vs_dT(const OraParams& P, double T) {
+  double a = (P.cpv - P.cl) / P.Rv;
+  double b = (P.Lref - (P.cpv - P.cl) * P.Tref) / P.Rv;
+  return rho_vs(P, T) * (a / T + b / (T * T) - 1.0 / T);
+}
+
+// internal energy density for a given temperature and vapour density
+// (energy-temperature relation without the kinetic part)
+template <class R> R rho_e_of(const OraParams& P, R rd, R rm, R rr, R rv, R T) {
+  R Cv = P.cvd * rd + P.cvv * rv + P.cl * (rm - rv + rr);
+  return Cv * (T - P.Tref) + rv * (P.Lref - P.Rv * P.Tref);
+}
+
+struct SplitOut { double T, rv; int iters; int ok; };
+
+// Implicit condensation split (Section 2.2), in plain double precision.
+// The map T -> rho e is strictly increasing on both branches, so the solution
+// is unique.  All-vapour temperature first; if the air is not saturated there,
+// that is the answer.  Otherwise Newton on
+//   f(T) = rho_e_of(rho_v = rho_vs(T), T) - rho e,
+// kept inside a bracket by bisection, then polished to the last ulp.
+SplitOut split_double(const OraParams& P, double rd, double rm, double rr, double re) {
+  SplitOut o{0, 0, 0, 1};
+  double Cu = P.cvd * rd + P.cvv * rm + P.cl * rr;
+  double Tu = P.Tref + (re - rm * (P.Lref - P.Rv * P.Tref)) / Cu;
+  if (!std::isfinite(Tu) || !(Cu > 0)) { o.T = Tu; o.rv = rm; o.ok = 0; return o; }
+  if (Tu > 0 && rm <= rho_vs(P, Tu)) { o.T = Tu; o.rv = rm; return o; }
+  auto f = [&](double T) { return rho_e_of(P, rd, rm, rr, rho_vs(P, T), T) - re; };
+  // Saturated.  Below T_floor = 50 K the state is rejected: if the all-vapour
+  // temperature is that low, the root must lie above the floor.
+  const double T_floor = 50.0;
+  if (!(Tu > T_floor)) {
+    if (!(f(T_floor) < 0.0)) { o.T = Tu; o.rv = rm; o.ok = 0; return o; }
+    Tu = T_floor;
+  }
+  auto fp = [&](double T) {
+    double rv = rho_vs(P, T);
+    double Cv = P.cvd * rd + P.cvv * rv + P.cl * (rm - rv + rr);
+    return Cv + drho_vs_dT(P, T) * ((P.cvv - P.cl) * (T - P.Tref) + P.Lref - P.Rv * P.Tref);
+  };
+  // bracket: f(Tu) < 0; march up until f > 0
+  double lo = Tu, hi = Tu + 1.0;
+  int guard = 0;
+  while (f(hi) <= 0.0 && guard++ < 60) { lo = hi; hi = Tu + 2.0 * (hi - Tu); }
+  double T = lo;
+  int it = 0;
+  for (; it < 200; ++it) {
+    double fv = f(T);
+    if (fv < 0) lo = T; else hi = T;
+    double dT = -fv / fp(T);
+    if (std::fabs(dT) <= 1e-14 * T) { T += dT; break; }
+    double Tn = T + dT;
+    if (!(Tn > lo && Tn < hi)) Tn = 0.5 * (lo + hi);   // Newton left the bracket: bisect
+    T = Tn;
+    if (hi - lo <= 4e-16 * hi) break;
+  }
+  // polish: bracket the sign change between neighbouring doubles
+  double a = T, b = T;
+  int g1 = 0;
+  while (f(a) >= 0.0 && g1++ < 64) a = std::nextafter(a, 0.0);
+  b = std::nextafter(a, INFINITY);
+  int g2 = 0;
+  while (f(b) < 0.0 && g2++ < 64) { a = b; b = std::nextafter(b, INFINITY); }
+  T = (std::fabs(f(a)) <= std::fabs(f(b))) ? a : b;
+  o.T = T;
+  o.rv = rho_vs(P, T);
+  o.iters = it + 1;
+  return o;
+}
+
+// The same split for any scalar type: the root is found in double and the
+// tangent follows from the implicit function theorem, dT = -f_theta / f_T.
+template <class R> void split(const OraParams& P, R rd, R rm, R rr, R re, R* T, R* rv, int* ok,
+                              int* iters) {
+  SplitOut s = split_double(P, val(rd), val(rm), val(rr), val(re));
+  *ok = s.ok; *iters = s.iters;
+  R Cu = P.cvd * rd + P.cvv * rm + P.cl * rr;
+  R Tu = P.Tref + (re - rm * (P.Lref - P.Rv * P.Tref)) / Cu;
+  if (!s.ok || (val(Tu) > 0 && val(rm) <= val(rho_vs(P, R(val(Tu)))))) {
+    *T = Tu; *rv = rm; return;
+  }
+  R T0 = R(s.T);
+  R fth = rho_e_of(P, rd, rm, rr, R(s.rv), T0) - re;   // value ~0, tangent = f_theta . dtheta
+  double rvs = s.rv;
+  double Cv = P.cvd * val(rd) + P.cvv * rvs + P.cl * (val(rm) - rvs + val(rr));
+  double fT = Cv + drho_vs_dT(P, s.T) * ((P.cvv - P.cl) * (s.T - P.Tref) + P.Lref - P.Rv * P.Tref);
+  R Tt = T0 - (fth - R(val(fth))) / fT;   // value s.T, tangent -f_theta/f_T
+  *T = Tt;
+  *rv = rho_vs(P, Tt);
+}
+
+// ---------------------------------------------------------------------------
+// the discretisation context
+// ---------------------------------------------------------------------------
+struct Ctx {
+  OraMesh M;
+  OraParams P;
+  Tables tab;
+  int nvars, np, ne, d, k;
+  double h[3];
+  std::vector<double> bg_rd, bg_rm, bg_rr, bg_E, bg_p;   // per node height
+  long iters_total = 0;
+  int max_iters = 0;
+  int bad = 0;
+};
+
+// node multi-index: n = i + (k+1)(j + (k+1) l), axis 0 fastest
+inline int node_axis(int n, int axis, int p1) {
+  for (int a = 0; a < axis; ++a) n /= p1;
+  return n % p1;
+}
+inline int node_set_axis(int n, int axis, int val_, int p1) {
+  int stride = 1;
+  for (int a = 0; a < axis; ++a) stride *= p1;
+  int cur = (n / stride) % p1;
+  return n + (val_ - cur) * stride;
+}
+inline int elem_axis(const Ctx& c, int e, int axis) {
+  for (int a = 0; a < axis; ++a) e /= c.M.n[a];
+  return e % c.M.n[axis];
+}
+inline int elem_shift(const Ctx& c, int e, int axis, int delta) {
+  int stride = 1;
+  for (int a = 0; a < axis; ++a) stride *= c.M.n[a];
+  int cur = elem_axis(c, e, axis);
+  int nxt = (cur + delta + c.M.n[axis]) % c.M.n[axis];
+  return e + (nxt - cur) * stride;
+}
+inline int height_of(const Ctx& c, int e, int n) {
+  int p1 = c.k + 1;
+  return elem_axis(c, e, c.d - 1) * p1 + node_axis(n, c.d - 1, p1);
+}
+
+// variable indices in the paper's order (rho_d', rho_m', [rho_r'], m_1..m_d, E')
+inline int v_rd() { return 0; }
+inline int v_rm() { return 1; }
+inline int v_rr(const Ctx& c) { return c.P.rain ? 2 : -1; }
+inline int v_m(const Ctx& c, int i) { return (c.P.rain ? 3 : 2) + i; }
+inline int v_E(const Ctx& c) { return c.nvars - 1; }
+
+// everything the flux, wave speed and sources need at one node
+template <class R> struct Point {
+  R rd, rm, rr, rho, m[3], u[3], E, T, rv, rc, pp, cm, vr;
+  R F[3][8];   // F[j][v]
+  R G[8];
+  R lam[3];    // |u_j| + |v_r delta_jz| + c_m
+};
+
+// Pointwise state, split, fluxes (Section 2.3 perturbation form) and sources.
+template <class R> void pointwise(Ctx& c, const R* Uq, int iz, Point<R>& q) {
+  const OraParams& P = c.P;
+  int d = c.d;
+  R rdp = Uq[v_rd()], rmp = Uq[v_rm()];
+  R rrp = P.rain ? Uq[v_rr(c)] : R(0.0);
+  q.rd = c.bg_rd[iz] + rdp;
+  q.rm = c.bg_rm[iz] + rmp;
+  q.rr = P.rain ? R(c.bg_rr[iz]) + rrp : R(0.0);
+  q.rho = q.rd + q.rm + q.rr;                                   // total density
+  R ke = R(0.0);
+  for (int i = 0; i < d; ++i) {
+    q.m[i] = Uq[v_m(c, i)];
+    q.u[i] = q.m[i] / q.rho;
+    ke += 0.5 * q.m[i] * q.u[i];
+  }
+  q.E = c.bg_E[iz] + Uq[v_E(c)];
+  R re = q.E - ke;                                              // rho e = E - rho u.u/2
+  int ok = 1, iters = 0;
+  split(P, q.rd, q.rm, q.rr, re, &q.T, &q.rv, &ok, &iters);
+  c.iters_total += iters;
+  c.max_iters = std::max(c.max_iters, iters);
+  if (!ok) c.bad++;
+  q.rc = q.rm - q.rv;
+  R p = (q.rd * P.Rd + q.rv * P.Rv) * q.T;                      // equation of state
+  q.pp = p - c.bg_p[iz];
+  R Cv = P.cvd * q.rd + P.cvv * q.rv + P.cl * (q.rc + q.rr);
+  R gam = 1.0 + (q.rd * P.Rd + q.rv * P.Rv) / Cv;               // moist isentropic factor
+  q.cm = sqrt(gam * p / q.rho);
+  // terminal rain speed
+  if (!P.rain) q.vr = R(0.0);
+  else if (P.vr_mode == 0) q.vr = R(P.vr_const);
+  else {
+    double pref = std::pow(M_PI * P.rho_w * P.N0r, -0.125) * P.v0r * std::tgamma(4.5) / 6.0;
+    q.vr = pref * pw(pos(q.rr), 0.125);
+  }
+  int z = d - 1;
+  R u2 = R(0.0);
+  for (int i = 0; i < d; ++i) u2 += q.u[i] * q.u[i];
+  for (int j = 0; j < d; ++j) {
+    R vz = (j == z) ? q.vr : R(0.0);
+    q.F[j][v_rd()] = q.rd * q.u[j];
+    q.F[j][v_rm()] = q.rm * q.u[j];
+    if (P.rain) q.F[j][v_rr(c)] = q.rr * (q.u[j] - vz);
+    for (int i = 0; i < d; ++i)
+      q.F[j][v_m(c, i)] = q.m[i] * q.u[j] + (i == j ? q.pp : R(0.0)) - q.rr * vz * q.u[i];
+    q.F[j][v_E(c)] = (q.E + c.bg_p[iz] + q.pp) * q.u[j]
+                     - (P.cl * (q.T - P.Tref) + 0.5 * u2) * q.rr * vz;
+    q.lam[j] = absr(q.u[j]) + absr(vz) + q.cm;
+  }
+  // sources: gravity and Kessler microphysics (Section 2.1)
+  for (int v = 0; v < c.nvars; ++v) q.G[v] = R(0.0);
+  R rhop = rdp + rmp + rrp;
+  q.G[v_m(c, z)] = -rhop * P.g;
+  q.G[v_E(c)] = -q.rho * P.g * q.u[z];
+  if (P.rain) {
+    R rrp_ = pos(q.rr);
+    R Sev = (3.86e-3 - 9.41e-5 * (q.T - P.Tref)) * (1.0 + 9.1 * pw(rrp_, 3.0 / 16.0))
+            * (rho_vs(P, q.T) - q.rv) * pw(rrp_, 0.5);
+    R Sau = 1e-3 * pos(q.rc - P.q_au * q.rho);
+    R Sac = 1.72 * q.rc * pw(rrp_, 7.0 / 8.0);
+    q.G[v_rm()] = Sev - Sau - Sac;
+    q.G[v_rr(c)] = Sau + Sac - Sev;
+  }
+}
+
+// Lax-Friedrichs flux with normal +e_j: (F(U-) + F(U+)).n / 2 + Lambda/2 (U- - U+)
+template <class R> void lf_flux(const Ctx& c, const Point<R>& a, const R* Ua, const Point<R>& b,
+                                const R* Ub, int j, R* Fs) {
+  R L = max_minus(a.lam[j], b.lam[j]);
+  for (int v = 0; v < c.nvars; ++v) Fs[v] = 0.5 * (a.F[j][v] + b.F[j][v]) + 0.5 * L * (Ua[v] - Ub[v]);
+}
+
+
+// ---------------------------------------------------------------------------
+// right-hand side (Section 3.2 weak form with the diagonal mass of Section 3.3)
+// ---------------------------------------------------------------------------
+// Slip-wall ghost (Section 3.2): momentum reflected in the wall normal e_j,
+// all other components copied.
+template <class R> void ghost_state(const Ctx& c, const R* Ua, int j, R* Ug) {
+  for (int v = 0; v < c.nvars; ++v) Ug[v] = Ua[v];
+  Ug[v_m(c, j)] = -Ua[v_m(c, j)];
+}
+
+// dU/dt = M^{-1} [ (F, grad V)_K - sum_faces (F_n, [V]) + (G, V)_K ] on every node.
+template <class R> void rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
+  const int nv = c.nvars, np = c.np, ne = c.ne, d = c.d, k = c.k, p1 = k + 1;
+  const long N = (long)ne * np;
+  auto at = [&](int v, int e, int n) -> long { return (long)v * N + (long)e * np + n; };
+  // 1. pointwise reconstruction + fluxes at every node
+  std::vector<Point<R>> q(N);
+  std::vector<R> Uq(nv);
+  for (int e = 0; e < ne; ++e)
+    for (int n = 0; n < np; ++n) {
+      for (int v = 0; v < nv; ++v) Uq[v] = U[at(v, e, n)];
+      pointwise(c, Uq.data(), height_of(c, e, n), q[(long)e * np + n]);
+    }
+  // 2. volume term: sum_j (2/h_j) sum_a Dhat[i_j][a] F_j(node a on the j-line)
+  for (int e = 0; e < ne; ++e)
+    for (int n = 0; n < np; ++n)
+      for (int v = 0; v < nv; ++v) {
+        R acc = R(0.0);
+        for (int j = 0; j < d; ++j) {
+          int ij = node_axis(n, j, p1);
+          R s = R(0.0);
+          for (int a = 0; a < p1; ++a)
+            s += c.tab.Dhat[ij * p1 + a] * q[(long)e * np + node_set_axis(n, j, a, p1)].F[j][v];
+          acc += (2.0 / c.h[j]) * s;
+        }
+        dU[at(v, e, n)] = acc;
+      }
+  // 3. faces with normal +e_j between K- = e and K+ = its +j neighbour
+  std::vector<R> Um(nv), Up(nv), Fs(nv);
+  double wflux = 0.0;
+  for (int j = 0; j < d; ++j) {
+    double liftK = (2.0 / c.h[j]) / c.tab.w[k];
+    double lift0 = (2.0 / c.h[j]) / c.tab.w[0];
+    bool wall = c.M.bc[j] == 1;
+    for (int e = 0; e < ne; ++e) {
+      int ej = elem_axis(c, e, j);
+      bool top = ej == c.M.n[j] - 1;
+      bool bottom = ej == 0;
+      for (int n = 0; n < np; ++n) {
+        if (node_axis(n, j, p1) != k) continue;     // nodes of e on its +j face
+        int nb = node_set_axis(n, j, 0, p1);        // matching node on the other side
+        // face weight times face Jacobian, for the boundary flux diagnostic
+        double wf = 1.0;
+        for (int a = 0; a < d; ++a)
+          if (a != j) wf *= c.tab.w[node_axis(n, a, p1)] * 0.5 * c.h[a];
+        for (int v = 0; v < nv; ++v) Um[v] = U[at(v, e, n)];
+        const Point<R>& qm = q[(long)e * np + n];
+        if (wall && top) {
+          // top wall: U+ is the ghost of U-; only K- is updated
+          ghost_state(c, Um.data(), j, Up.data());
+          Point<R> qg;
+          pointwise(c, Up.data(), height_of(c, e, n), qg);
+          lf_flux(c, qm, Um.data(), qg, Up.data(), j, Fs.data());
+          for (int v = 0; v < nv; ++v) dU[at(v, e, n)] -= liftK * Fs[v];
+          if (c.P.rain) wflux += wf * val(Fs[v_rr(c)]);
+        } else {
+          int e2 = elem_shift(c, e, j, +1);
+          for (int v = 0; v < nv; ++v) Up[v] = U[at(v, e2, nb)];
+          const Point<R>& qp = q[(long)e2 * np + nb];
+          lf_flux(c, qm, Um.data(), qp, Up.data(), j, Fs.data());
+          for (int v = 0; v < nv; ++v) {
+            dU[at(v, e, n)] -= liftK * Fs[v];
+            dU[at(v, e2, nb)] += lift0 * Fs[v];
+          }
+        }
+        if (wall && bottom) {
+          // bottom wall of e: K- is the ghost below, K+ = e at its node index 0
+          int n0 = node_set_axis(n, j, 0, p1);
+          std::vector<R> Ui(nv), Ug(nv);
+          for (int v = 0; v < nv; ++v) Ui[v] = U[at(v, e, n0)];
+          ghost_state(c, Ui.data(), j, Ug.data());
+          Point<R> qg;
+          pointwise(c, Ug.data(), height_of(c, e, n0), qg);
+          const Point<R>& qi = q[(long)e * np + n0];
+          lf_flux(c, qg, Ug.data(), qi, Ui.data(), j, Fs.data());
+          for (int v = 0; v < nv; ++v) dU[at(v, e, n0)] += lift0 * Fs[v];
+          if (c.P.rain) wflux -= wf * val(Fs[v_rr(c)]);
+        }
+      }
+    }
+  }
+  // 4. sources
+  for (int e = 0; e < ne; ++e)
+    for (int n = 0; n < np; ++n)
+      for (int v = 0; v < nv; ++v) dU[at(v, e, n)] += q[(long)e * np + n].G[v];
+  if (wall_rain_flux) *wall_rain_flux = wflux;
+}
+
+// SSP Runge-Kutta step in Shu-Osher form (Section 3.3 remark): SSPRK(4,3) of
+// Kraaijevanger, or the three-stage SSPRK(3,3).
+template <class R> void rk_step(Ctx& c, R* U, double dt, int scheme, double* outflow) {
+  const long N = (long)c.ne * c.np * c.nvars;
+  std::vector<R> u0(U, U + N), us(N), L(N);
+  double fl = 0.0, f = 0.0;
+  if (scheme == 0) {
+    // u1 = u0 + dt/2 L(u0); u2 = u1 + dt/2 L(u1);
+    // u3 = 2/3 u0 + 1/3 u2 + dt/6 L(u2); u4 = u3 + dt/2 L(u3)
+    rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
+    for (long i = 0; i < N; ++i) us[i] = u0[i] + (0.5 * dt) * L[i];
+    rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    for (long i = 0; i < N; ++i) us[i] = us[i] + (0.5 * dt) * L[i];
+    rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    for (long i = 0; i < N; ++i) us[i] = (2.0 / 3.0) * u0[i] + (1.0 / 3.0) * us[i] + (dt / 6.0) * L[i];
+    rhs(c, us.data(), L.data(), &f); fl += f / 2.0;
+    for (long i = 0; i < N; ++i) U[i] = us[i] + (0.5 * dt) * L[i];
+  } else {
+    // u1 = u0 + dt L(u0); u2 = 3/4 u0 + 1/4 u1 + dt/4 L(u1);
+    // u3 = 1/3 u0 + 2/3 u2 + 2/3 dt L(u2)
+    rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
+    for (long i = 0; i < N; ++i) us[i] = u0[i] + dt * L[i];
+    rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    for (long i = 0; i < N; ++i) us[i] = 0.75 * u0[i] + 0.25 * us[i] + (0.25 * dt) * L[i];
+    rhs(c, us.data(), L.data(), &f); fl += f * (2.0 / 3.0);
+    for (long i = 0; i < N; ++i) U[i] = (1.0 / 3.0) * u0[i] + (2.0 / 3.0) * us[i] + ((2.0 / 3.0) * dt) * L[i];
+  }
+  if (outflow) *outflow = fl * dt;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C entry points used by the tests through ctypes
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int ora_tables(int k, double* x, double* w, double* D, double* Dhat) {
+  if (k < 1 || k > 12) return -1;
+  Tables t = make_tables(k);
+  int p1 = k + 1;
+  std::memcpy(x, t.x.data(), p1 * sizeof(double));
+  std::memcpy(w, t.w.data(), p1 * sizeof(double));
+  std::memcpy(D, t.D.data(), p1 * p1 * sizeof(double));
+  std::memcpy(Dhat, t.Dhat.data(), p1 * p1 * sizeof(double));
+  return 0;
+}
+
+double ora_esat(const OraParams* P, double T) { return esat(*P, T); }
+double ora_rho_vs(const OraParams* P, double T) { return rho_vs(*P, T); }
+
+// Split of one state; returns the Newton iteration count (0 on the unsaturated
+// branch) or -1 if no temperature above 50 K solves the system.
+int ora_split(const OraParams* P, double rd, double rm, double rr, double re, double* T,
+              double* rv, double* rc) {
+  SplitOut s = split_double(*P, rd, rm, rr, re);
+  *T = s.T; *rv = s.rv; *rc = rm - s.rv;
+  return s.ok ? s.iters : -1;
+}
+
+// tangent of the split: (dT, drho_v) along (drd, drm, drr, dre)
+int ora_split_jvp(const OraParams* P, double rd, double rm, double rr, double re, double drd,
+                  double drm, double drr, double dre, double* T, double* dT, double* rv,
+                  double* drv) {
+  Dual Tt, rvt;
+  int ok, it;
+  split(*P, Dual(rd, drd), Dual(rm, drm), Dual(rr, drr), Dual(re, dre), &Tt, &rvt, &ok, &it);
+  *T = Tt.v; *dT = Tt.d; *rv = rvt.v; *drv = rvt.d;
+  return ok ? 0 : -1;
+}
+
+// Set up a mesh, tables and background.  The background arrays hold rho_d,
+// rho_m, rho_r, E at the n_z (k+1) node heights; the background pressure is the
+// equation of state applied to the split of the background state.
+void* ora_create(const OraMesh* M, const OraParams* P, int nvars, const double* rd,
+                 const double* rm, const double* rr, const double* E) {
+  if (M->dim < 2 || M->dim > 3 || M->order < 1 || M->order > 8) return nullptr;
+  if (nvars != (P->rain ? 4 : 3) + M->dim) return nullptr;
+  Ctx* c = new Ctx();
+  c->M = *M; c->P = *P;
+  c->d = M->dim; c->k = M->order; c->nvars = nvars;
+  c->tab = make_tables(c->k);
+  c->np = 1; c->ne = 1;
+  for (int a = 0; a < c->d; ++a) {
+    c->np *= (c->k + 1);
+    c->ne *= M->n[a];
+    c->h[a] = (M->hi[a] - M->lo[a]) / M->n[a];
+  }
+  int nzq = M->n[c->d - 1] * (c->k + 1);
+  c->bg_rd.assign(rd, rd + nzq); c->bg_rm.assign(rm, rm + nzq);
+  c->bg_rr.assign(rr, rr + nzq); c->bg_E.assign(E, E + nzq);
+  c->bg_p.assign(nzq, 0.0);
+  for (int iz = 0; iz < nzq; ++iz) {
+    double rrr = P->rain ? rr[iz] : 0.0;
+    SplitOut s = split_double(*P, rd[iz], rm[iz], rrr, E[iz]);
+    c->bg_p[iz] = (rd[iz] * P->Rd + s.rv * P->Rv) * s.T;
+  }
+  return c;
+}
+
+void ora_destroy(void* h) { delete (Ctx*)h; }
+
+void ora_background_pressure(void* h, double* p) {
+  Ctx* c = (Ctx*)h;
+  std::copy(c->bg_p.begin(), c->bg_p.end(), p);
+}
+
+// split of every node: T, rho_v, rho_c, p' and c_m in U's node order
+int ora_split_field(void* h, const double* U, double* T, double* rv, double* rc, double* pp,
+                    double* cm) {
+  Ctx* c = (Ctx*)h;
+  long N = (long)c->ne * c->np;
+  std::vector<double> Uq(c->nvars);
+  int bad = c->bad;
+  for (int e = 0; e < c->ne; ++e)
+    for (int n = 0; n < c->np; ++n) {
+      long i = (long)e * c->np + n;
+      for (int v = 0; v < c->nvars; ++v) Uq[v] = U[(long)v * N + i];
+      Point<double> q;
+      pointwise(*c, Uq.data(), height_of(*c, e, n), q);
+      if (T) T[i] = q.T;
+      if (rv) rv[i] = q.rv;
+      if (rc) rc[i] = q.rc;
+      if (pp) pp[i] = q.pp;
+      if (cm) cm[i] = q.cm;
+    }
+  return c->bad - bad;
+}
+
+int ora_rhs(void* h, const double* U, double* dU, double* wall_rain_flux) {
+  Ctx* c = (Ctx*)h;
+  int bad = c->bad;
+  rhs(*c, U, dU, wall_rain_flux);
+  return c->bad - bad;
+}
+
+// nsteps steps of size dt in place; outflow accumulates dt * sum_s b_s * (wall
+// rain flux of stage s), the total rain mass that left through the walls
+int ora_rk_step(void* h, double* U, double dt, int nsteps, int scheme, double* outflow) {
+  Ctx* c = (Ctx*)h;
+  int bad = c->bad;
+  double acc = 0.0;
+  for (int s = 0; s < nsteps; ++s) {
+    double f = 0.0;
+    rk_step(*c, U, dt, scheme, &f);
+    acc += f;
+  }
+  if (outflow) *outflow = acc;
+  return c->bad - bad;
+}
+
+// exact directional derivative of the right-hand side: JV = d rhs(U + eps V)/d eps
+int ora_rhs_jvp(void* h, const double* U, const double* V, double* dU, double* JV) {
+  Ctx* c = (Ctx*)h;
+  long N = (long)c->ne * c->np * c->nvars;
+  std::vector<Dual> Ud(N), Rd(N);
+  for (long i = 0; i < N; ++i) Ud[i] = Dual(U[i], V[i]);
+  int bad = c->bad;
+  rhs(*c, Ud.data(), Rd.data(), nullptr);
+  for (long i = 0; i < N; ++i) { if (dU) dU[i] = Rd[i].v; JV[i] = Rd[i].d; }
+  return c->bad - bad;
+}
+
+// nsteps RK steps of (U, V) in place: U the state, V its tangent
+int ora_rk_jvp(void* h, double* U, double* V, double dt, int nsteps, int scheme) {
+  Ctx* c = (Ctx*)h;
+  long N = (long)c->ne * c->np * c->nvars;
+  std::vector<Dual> Ud(N);
+  for (long i = 0; i < N; ++i) Ud[i] = Dual(U[i], V[i]);
+  int bad = c->bad;
+  for (int s = 0; s < nsteps; ++s) rk_step(*c, Ud.data(), dt, scheme, nullptr);
+  for (long i = 0; i < N; ++i) { U[i] = Ud[i].v; V[i] = Ud[i].d; }
+  return c->bad - bad;
+}
+
+// M_d = sum w J rho_d', M_w = sum w J (rho_m' + rho_r'), and the instantaneous
+// rain mass flux out through the walls
+void ora_mass(void* h, const double* U, double* out3) {
+  Ctx* c = (Ctx*)h;
+  long N = (long)c->ne * c->np;
+  int p1 = c->k + 1;
+  double J = 1.0;
+  for (int a = 0; a < c->d; ++a) J *= 0.5 * c->h[a];
+  double md = 0.0, mw = 0.0;
+  for (int e = 0; e < c->ne; ++e)
+    for (int n = 0; n < c->np; ++n) {
+      double w = J;
+      for (int a = 0; a < c->d; ++a) w *= c->tab.w[node_axis(n, a, p1)];
+      long i = (long)e * c->np + n;
+      md += w * U[i];
+      mw += w * (U[N + i] + (c->P.rain ? U[2 * N + i] : 0.0));
+    }
+  out3[0] = md; out3[1] = mw;
+  std::vector<double> dU(N * c->nvars);
+  double f = 0.0;
+  rhs(*c, U, dU.data(), &f);
+  out3[2] = f;
+}
+
+// pointwise physical fluxes F[j*nvars+v], sources G[v] and wave speeds lam[j]
+// of one state Uq at node height iz
+void ora_point(void* h, const double* Uq, int iz, double* F, double* G, double* lam) {
+  Ctx* c = (Ctx*)h;
+  Point<double> q;
+  pointwise(*c, Uq, iz, q);
+  for (int j = 0; j < c->d; ++j) {
+    for (int v = 0; v < c->nvars; ++v) F[j * c->nvars + v] = q.F[j][v];
+    lam[j] = q.lam[j];
+  }
+  for (int v = 0; v < c->nvars; ++v) G[v] = q.G[v];
+}
+
+// Lax-Friedrichs flux with normal +e_j between the states Um (node height
+// izm) and Up (izp)
+void ora_face(void* h, const double* Um, int izm, const double* Up, int izp, int j, double* Fs) {
+  Ctx* c = (Ctx*)h;
+  Point<double> a, b;
+  pointwise(*c, Um, izm, a);
+  pointwise(*c, Up, izp, b);
+  lf_flux(*c, a, Um, b, Up, j, Fs);
+}
+
+void ora_stats(void* h, long* iters_total, int* max_iters, int* bad) {
+  Ctx* c = (Ctx*)h;
+  *iters_total = c->iters_total; *max_iters = c->max_iters; *bad = c->bad;
+}
+
+}  // extern "C"

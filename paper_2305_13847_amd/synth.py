@@ -1,0 +1,404 @@
+"""Seeded synthetic inputs for the moist DG hot path.
+
+This module builds the arrays that both the HIP library and the CPU checker
+receive: mesh descriptions, hydrostatic-like background profiles at the node
+heights, and perturbation states in the library's ``U[v][e][n]`` layout.  It
+holds no part of the discretisation itself (no saturation inversion, no flux,
+no quadrature weights, no time stepping).  States are *constructed* from a
+temperature and a water partition; the partition uses the Magnus-type fit of
+the saturation vapour pressure (Alduchov & Eskridge 1996), deliberately not the
+Clausius-Clapeyron form of the paper, so that whichever side inverts the state
+later does so with its own saturation law.  The conserved energy is then the
+paper's definition of E (Section 2, energy-temperature relation).
+
+Shapes follow the paper's workloads: the rising moist bubble (Section 4.2,
+Appendix B.2), the warm-rain thermals (Sections 4.5-4.6) and smooth periodic
+fields for small parity cases.  Every random number comes from numpy's PCG64
+with a recorded seed.
+"""
+from __future__ import annotations
+
+import dataclasses
+import hashlib
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+# Thermodynamic constants as printed in the paper's appendix table; g is not in
+# that table and is the usual 9.81 m s^-2.
+C = dict(cl=4218.0, cpd=1005.0, cpv=1850.0, cvd=718.0, cvv=1390.0,
+         eref=610.7, Lref=2.835e6, Rd=287.05, Rv=461.51, Tref=273.15,
+         pref=1.0e5, g=9.81)
+
+PERIODIC, WALL = 0, 1
+C_BOUND = 350.0   # upper bound on the sound speed used for the time step
+
+
+@dataclasses.dataclass
+class Mesh:
+    """Structured box of ``n`` elements per axis; the last axis is vertical."""
+    dim: int
+    n: Sequence[int]
+    lo: Sequence[float]
+    hi: Sequence[float]
+    bc: Sequence[int]
+    order: int
+
+    @property
+    def ne(self) -> int:
+        return int(np.prod(self.n))
+
+    @property
+    def npe(self) -> int:
+        return (self.order + 1) ** self.dim
+
+    @property
+    def h(self) -> np.ndarray:
+        return (np.asarray(self.hi, float) - np.asarray(self.lo, float)) / np.asarray(self.n, float)
+
+    @property
+    def nzq(self) -> int:
+        """Number of distinct node heights (vertical elements x nodes per line)."""
+        return self.n[-1] * (self.order + 1)
+
+
+@dataclasses.dataclass
+class Case:
+    name: str
+    mesh: Mesh
+    nvars: int
+    rain: int
+    g: float
+    vr_const: float
+    bg: Dict[str, np.ndarray]         # rho_d, rho_m, rho_r, E at node heights
+    U: np.ndarray                     # (nvars, ne, npe) float64 perturbation state
+    dt: float
+    nsteps: int
+    seed: int
+    info: Dict[str, float] = dataclasses.field(default_factory=dict)
+    bg_full: Optional[Dict[str, np.ndarray]] = None   # adds T and p of the construction
+
+    def digest(self) -> str:
+        h = hashlib.sha256()
+        for k in ("rho_d", "rho_m", "rho_r", "E"):
+            h.update(np.ascontiguousarray(self.bg[k]).tobytes())
+        h.update(np.ascontiguousarray(self.U).tobytes())
+        return h.hexdigest()[:16]
+
+
+# ----------------------------------------------------------------------------
+# geometry
+# ----------------------------------------------------------------------------
+def lobatto_points(k: int) -> np.ndarray:
+    """Gauss-Lobatto points on [-1, 1]: +-1 and the roots of P_k' (numpy)."""
+    from numpy.polynomial import legendre as L
+    if k == 1:
+        return np.array([-1.0, 1.0])
+    c = np.zeros(k + 1)
+    c[-1] = 1.0
+    inner = np.sort(np.real(L.legroots(L.legder(c))))
+    return np.concatenate([[-1.0], inner, [1.0]])
+
+
+def node_coords(mesh: Mesh) -> List[np.ndarray]:
+    """Physical coordinates of every node, one (ne, npe) array per axis."""
+    k, d = mesh.order, mesh.dim
+    xi = lobatto_points(k)
+    p1 = k + 1
+    # element multi-index (x fastest) and node multi-index (i fastest)
+    e_idx = np.unravel_index(np.arange(mesh.ne), tuple(reversed(mesh.n)))
+    e_idx = list(reversed(e_idx))                   # e_idx[a] = element index along axis a
+    n_idx = np.unravel_index(np.arange(p1 ** d), (p1,) * d)
+    n_idx = list(reversed(n_idx))                   # n_idx[a] = node index along axis a
+    h = mesh.h
+    out = []
+    for a in range(d):
+        x = (mesh.lo[a] + (e_idx[a][:, None] + 0.5 * (xi[n_idx[a]][None, :] + 1.0)) * h[a])
+        out.append(x)
+    return out
+
+
+def node_heights(mesh: Mesh) -> np.ndarray:
+    """Height of every vertical node index iz = ez*(k+1) + l."""
+    xi = lobatto_points(mesh.order)
+    hz = mesh.h[-1]
+    ez = np.arange(mesh.n[-1])
+    z = mesh.lo[-1] + (ez[:, None] + 0.5 * (xi[None, :] + 1.0)) * hz
+    return z.reshape(-1)
+
+
+def height_index(mesh: Mesh) -> np.ndarray:
+    """(ne, npe) map from a node to its vertical index iz."""
+    p1 = mesh.order + 1
+    ez = np.arange(mesh.ne) // int(np.prod(mesh.n[:-1]))
+    l = np.arange(p1 ** mesh.dim) // (p1 ** (mesh.dim - 1))
+    return ez[:, None] * p1 + l[None, :]
+
+
+# ----------------------------------------------------------------------------
+# state construction
+# ----------------------------------------------------------------------------
+def magnus_rho_vs(T):
+    """Approximate saturation vapour density, Magnus fit over liquid water."""
+    es = 610.94 * np.exp(17.625 * (T - 273.15) / (T - 30.11))
+    return es / (C["Rv"] * T)
+
+
+def energy(rho_d, rho_v, rho_c, rho_r, T, m2_over_rho=0.0):
+    """Paper's total energy density for a given temperature and partition."""
+    Cv = C["cvd"] * rho_d + C["cvv"] * rho_v + C["cl"] * (rho_c + rho_r)
+    return Cv * (T - C["Tref"]) + rho_v * (C["Lref"] - C["Rv"] * C["Tref"]) + 0.5 * m2_over_rho
+
+
+def energy_dT(rho_d, rho_m, rho_r, T):
+    """d energy / dT at fixed densities, with the Magnus partition."""
+    rvs = magnus_rho_vs(T)
+    sat = rho_m > rvs
+    Cv = np.where(sat, C["cvd"] * rho_d + C["cvv"] * rvs + C["cl"] * (rho_m - rvs + rho_r),
+                  C["cvd"] * rho_d + C["cvv"] * rho_m + C["cl"] * rho_r)
+    # d rvs/dT of the Magnus fit
+    a, b = 17.625, 30.11
+    dlnes = a * (273.15 - b) / (T - b) ** 2
+    drvs = rvs * (dlnes - 1.0 / T)
+    Leff = (C["cvv"] - C["cl"]) * (T - C["Tref"]) + C["Lref"] - C["Rv"] * C["Tref"]
+    return Cv + np.where(sat, drvs * Leff, 0.0)
+
+
+def partitioned_energy(rho_d, rho_m, rho_r, T, m2_over_rho=0.0):
+    rvs = magnus_rho_vs(T)
+    rho_v = np.minimum(rho_m, rvs)
+    return energy(rho_d, rho_v, rho_m - rho_v, rho_r, T, m2_over_rho)
+
+
+def background(mesh: Mesh, Ts: float, ratio: Callable[[np.ndarray], np.ndarray],
+               lapse: float = 6.5e-3, p0: float = 1.0e5, g: float = 9.81) -> Dict[str, np.ndarray]:
+    """Hydrostatic-like background at node heights.
+
+    T(z) = Ts - lapse*z, rho_m = ratio(z) * rho_vs(T) with the Magnus fit, and
+    dp/dz = -g (rho_d + rho_m) integrated from p(0) = p0.  Only the arrays the
+    library consumes are returned (rho_d, rho_m, rho_r, E); the pressure is
+    reconstructed by each solver from these.
+    """
+    from scipy.integrate import solve_ivp
+    z = node_heights(mesh)
+
+    def parts(zz, p):
+        T = Ts - lapse * zz
+        rvs = magnus_rho_vs(T)
+        rm = ratio(np.asarray(zz)) * rvs
+        rv = np.minimum(rm, rvs)
+        rd = (p / T - C["Rv"] * rv) / C["Rd"]
+        return T, rd, rm, rv
+
+    def rhs(zz, p):
+        _, rd, rm, _ = parts(zz, p)
+        return -g * (rd + rm)
+
+    zs = np.unique(np.concatenate([[0.0], z]))
+    sol = solve_ivp(rhs, (0.0, float(zs[-1])), [p0], t_eval=zs, rtol=1e-12, atol=1e-9,
+                    method="DOP853")
+    p = np.interp(z, sol.t, sol.y[0])
+    T, rd, rm, rv = parts(z, p)
+    rc = rm - rv
+    E = energy(rd, rv, rc, 0.0, T)
+    return dict(rho_d=rd, rho_m=rm, rho_r=np.zeros_like(z), E=E, T=T, p=p)
+
+
+def bubble(X: List[np.ndarray], centre, radius, amp) -> np.ndarray:
+    """cos^2 bubble of the rising-thermal set-ups (Appendix B.2 shape)."""
+    L2 = sum(((X[a] - centre[a]) / radius) ** 2 for a in range(len(X)))
+    L = np.minimum(np.sqrt(L2), 1.0)
+    return amp * np.cos(0.5 * np.pi * L) ** 2
+
+
+def cfl_dt(mesh: Mesh, umax: float, vr: float, cfl: float) -> float:
+    k = mesh.order
+    return float(cfl * np.min(mesh.h) / ((2 * k + 1) * (C_BOUND + umax + vr)))
+
+
+def _layout(fields: List[np.ndarray]) -> np.ndarray:
+    return np.ascontiguousarray(np.stack(fields, axis=0), dtype=np.float64)
+
+
+def _bg_at_nodes(mesh: Mesh, bg: Dict[str, np.ndarray]) -> Dict[str, np.ndarray]:
+    iz = height_index(mesh)
+    return {k: v[iz] for k, v in bg.items()}
+
+
+def theta_to_state(mesh: Mesh, bg: Dict[str, np.ndarray], theta: np.ndarray,
+                   rain: bool) -> np.ndarray:
+    """Perturbation state for a potential-temperature perturbation at rest.
+
+    rho_d' = rho_m' = 0, m = 0 and E' = E(T_bg + T') - E_bg with
+    T' = theta' (p_bg/p_ref)^(R_d/c_pd).
+    """
+    b = _bg_at_nodes(mesh, bg)
+    Tp = theta * (b["p"] / C["pref"]) ** (C["Rd"] / C["cpd"])
+    E1 = partitioned_energy(b["rho_d"], b["rho_m"], b["rho_r"], b["T"] + Tp)
+    E0 = partitioned_energy(b["rho_d"], b["rho_m"], b["rho_r"], b["T"])
+    z = np.zeros_like(theta)
+    flds = [z, z.copy()] + ([z.copy()] if rain else []) + [z.copy() for _ in range(mesh.dim)] + [E1 - E0]
+    return _layout(flds)
+
+
+def theta_to_state_jvp(mesh: Mesh, bg: Dict[str, np.ndarray], theta: np.ndarray) -> np.ndarray:
+    """d E'/d theta' per node (the only component of U that depends on theta')."""
+    b = _bg_at_nodes(mesh, bg)
+    ex = (b["p"] / C["pref"]) ** (C["Rd"] / C["cpd"])
+    return energy_dT(b["rho_d"], b["rho_m"], b["rho_r"], b["T"] + theta * ex) * ex
+
+
+def add_noise(rng: np.random.Generator, U: np.ndarray, mesh: Mesh, b: Dict[str, np.ndarray],
+              rain: bool, level: float = 1e-4) -> None:
+    rho = b["rho_d"] + b["rho_m"]
+    scales = [b["rho_d"], b["rho_m"]] + ([1e-3 * np.ones_like(rho)] if rain else []) \
+        + [rho * 1.0] * mesh.dim + [b["E"]]
+    for v, s in enumerate(scales):
+        U[v] += level * s * rng.standard_normal(U[v].shape)
+
+
+# ----------------------------------------------------------------------------
+# the workloads
+# ----------------------------------------------------------------------------
+def _modes(rng, X, L, nmodes=3):
+    """Normalised sum of smooth periodic modes with integer wave vectors."""
+    s = np.zeros_like(X[0])
+    for _ in range(nmodes):
+        kv = rng.integers(1, 4, size=len(X))
+        w = rng.uniform(0.5, 1.0)
+        ph = rng.uniform(0.0, 2 * np.pi)
+        s += w * np.sin(sum(2 * np.pi * kv[a] * X[a] / L[a] for a in range(len(X))) + ph)
+    return s / np.max(np.abs(s))
+
+
+def periodic_smooth(n=(16, 16), order=2, seed=1, nsteps=10, sat_fraction=0.3,
+                    dim=2) -> Case:
+    """Smooth periodic moist fields on the unit square (or cube), g = 0.
+
+    Densities vary by 1%, the moist mixing ratio spans 2-20 g/kg, the velocity
+    is 1% of a 340 m/s sound speed, and the all-vapour temperature is shifted so
+    that about ``sat_fraction`` of the nodes are supersaturated before the
+    split (by the Magnus estimate).
+    """
+    rng = np.random.default_rng(seed)
+    mesh = Mesh(dim, list(n), [0.0] * dim, [1.0] * dim, [PERIODIC] * dim, order)
+    X = node_coords(mesh)
+    Ls = [1.0] * dim
+    s_d, s_q, s_T = (_modes(rng, X, Ls) for _ in range(3))
+    s_u = [_modes(rng, X, Ls) for _ in range(dim)]
+    rd = 1.16 * (1.0 + 1e-2 * s_d)
+    qm = 2e-3 + 18e-3 * (s_q - s_q.min()) / (s_q.max() - s_q.min())
+    rm = qm * rd
+    rho = rd + rm
+    u = [1e-2 * 340.0 * su for su in s_u]
+    m = [rho * ua for ua in u]
+    m2r = sum(ma * ma for ma in m) / rho
+
+    def frac_sat(T0):
+        Tu = T0 * (1.0 + 1e-2 * s_T)
+        return float(np.mean(rm > magnus_rho_vs(Tu)))
+
+    lo, hi = 250.0, 330.0           # frac_sat decreases with T0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        if frac_sat(mid) > sat_fraction:
+            lo = mid
+        else:
+            hi = mid
+    T0 = 0.5 * (lo + hi)
+    Tu = T0 * (1.0 + 1e-2 * s_T)
+    E = energy(rd, rm, 0.0, 0.0, Tu, m2r)     # all water counted as vapour
+    bg = dict(rho_d=np.full(mesh.nzq, rd.mean()), rho_m=np.full(mesh.nzq, rm.mean()),
+              rho_r=np.zeros(mesh.nzq), E=np.full(mesh.nzq, E.mean()))
+    U = _layout([rd - bg["rho_d"][0], rm - bg["rho_m"][0]] + m + [E - bg["E"][0]])
+    umax = float(np.max(np.sqrt(sum(ua * ua for ua in u))))
+    dt = cfl_dt(mesh, umax, 0.0, 0.2)
+    return Case("periodic-%dd-q%d-%s" % (dim, order, "x".join(map(str, n))), mesh, 3 + dim, 0,
+                0.0, 0.0, bg, U, dt, nsteps, seed,
+                info=dict(T0=T0, sat_fraction_magnus=frac_sat(T0)))
+
+
+def moist_bubble(n=(128, 64), order=4, seed=2, nsteps=1000, amp=2.0, centre=(10e3, 2e3),
+                 radius=2e3, noise=1e-4, ratio=1.3, Ts=300.0) -> Case:
+    """2D moist rising bubble in a cloudy background (Bryan-Fritsch shape).
+
+    Domain 20 km x 10 km, periodic in x, slip walls in z, gravity on, no rain.
+    """
+    rng = np.random.default_rng(seed)
+    mesh = Mesh(2, list(n), [0.0, 0.0], [20e3, 10e3], [PERIODIC, WALL], order)
+    bgf = background(mesh, Ts, lambda z: ratio + 0.0 * z)
+    X = node_coords(mesh)
+    th = bubble(X, centre, radius, amp)
+    U = theta_to_state(mesh, bgf, th, rain=False)
+    if noise:
+        add_noise(rng, U, mesh, _bg_at_nodes(mesh, bgf), rain=False, level=noise)
+    dt = cfl_dt(mesh, 5.0, 0.0, 0.2)
+    bg = {k: bgf[k] for k in ("rho_d", "rho_m", "rho_r", "E")}
+    return Case("bubble-2d-q%d-%dx%d" % (order, n[0], n[1]), mesh, 5, 0, C["g"], 0.0, bg, U, dt,
+                nsteps, seed, bg_full=bgf)
+
+
+def warm_rain_3d(n=(64, 64, 32), order=3, seed=3, nsteps=500, nbubbles=8, noise=1e-4,
+                 vr=5.0) -> Case:
+    """3D warm-rain thermals: Kessler on, rain falling at a constant 5 m/s.
+
+    Domain 20 x 20 x 10 km, periodic in x and y, slip walls in z.  The background
+    is subsaturated below ~1.5 km and cloudy above; eight +2 K bubbles at random
+    positions and a Gaussian rain blob 1 km above each.
+    """
+    rng = np.random.default_rng(seed)
+    mesh = Mesh(3, list(n), [0.0, 0.0, 0.0], [20e3, 20e3, 10e3], [PERIODIC, PERIODIC, WALL], order)
+    bgf = background(mesh, 300.0, lambda z: 0.8 + 0.25 * (1.0 + np.tanh((z - 1500.0) / 300.0)))
+    X = node_coords(mesh)
+    th = np.zeros_like(X[0])
+    rr = np.zeros_like(X[0])
+    for _ in range(nbubbles):
+        cx, cy = rng.uniform(2e3, 18e3, size=2)
+        cz = rng.uniform(1.5e3, 3e3)
+        th += bubble(X, (cx, cy, cz), 2e3, 2.0)
+        r2 = (X[0] - cx) ** 2 + (X[1] - cy) ** 2 + (X[2] - cz - 1e3) ** 2
+        rr += 1e-3 * np.exp(-r2 / 1e6)
+    U = theta_to_state(mesh, bgf, th, rain=True)
+    U[2] += rr
+    if noise:
+        add_noise(rng, U, mesh, _bg_at_nodes(mesh, bgf), rain=True, level=noise)
+    dt = cfl_dt(mesh, 5.0, vr, 0.2)
+    bg = {k: bgf[k] for k in ("rho_d", "rho_m", "rho_r", "E")}
+    return Case("rain-3d-q%d-%dx%dx%d" % (order, *n), mesh, 7, 1, C["g"], vr, bg, U, dt, nsteps, seed,
+                bg_full=bgf)
+
+
+def ensemble(nmembers=64, order=3, seed=4, nsteps=200, lo=16, hi=80) -> List[Case]:
+    """Uneven ensemble of 2D bubbles: nx = 2*U{lo..hi}, nz = nx/2 per member."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for mbr in range(nmembers):
+        nx = 2 * int(rng.integers(lo, hi + 1))
+        amp = float(rng.uniform(1.0, 3.0))
+        xc = float(rng.uniform(5e3, 15e3))
+        zc = float(rng.uniform(1.5e3, 3e3))
+        c = moist_bubble(n=(nx, nx // 2), order=order, seed=seed * 1000 + mbr, nsteps=nsteps,
+                         amp=amp, centre=(xc, zc))
+        c.name = "member%02d-" % mbr + c.name
+        out.append(c)
+    return out
+
+
+def adjoint_case(n=(64, 32), order=3, seed=5, nsteps=200) -> Case:
+    """The bubble used for gradients: dt fixed by the unperturbed set-up."""
+    return moist_bubble(n=n, order=order, seed=seed, nsteps=nsteps)
+
+
+def directions(mesh: Mesh, ndir=16, seed=6, centre=(10e3, 2e3)) -> np.ndarray:
+    """Seeded unit directions: sums of four 1 km Gaussian bumps near the bubble."""
+    rng = np.random.default_rng(seed)
+    X = node_coords(mesh)
+    out = []
+    for _ in range(ndir):
+        f = np.zeros_like(X[0])
+        for _ in range(4):
+            cx = centre[0] + rng.uniform(-2e3, 2e3)
+            cz = centre[1] + rng.uniform(-1e3, 2e3)
+            f += rng.standard_normal() * np.exp(-((X[0] - cx) ** 2 + (X[1] - cz) ** 2) / 1e6)
+        out.append(f / np.sqrt(np.sum(f * f)))
+    return np.stack(out)
