@@ -1,0 +1,186 @@
+/*
+ * dg.h -- C interface of libdgmoist: the explicit discontinuous Galerkin
+ * right-hand side of the moist compressible Euler equations with implicit
+ * condensation and optional Kessler warm rain, on MI355X (gfx950).
+ *
+ * The operations follow the paper's statement of the problem
+ * (Hittmeir, Lederer, Schoeberl, von Wahl, arXiv 2305.13847):
+ *   - unknowns U = (rho_d', rho_m', [rho_r'], m_1..m_d, E'), perturbations from
+ *     a hydrostatic background that depends on height only (Section 2.3,
+ *     perturbation formulation; Section 3, balance-law form);
+ *   - rho_v, rho_c and T are recovered pointwise from the implicit
+ *     condensation system (Section 2.2) before every right-hand side
+ *     evaluation (Section 3.4);
+ *   - DG weak form with the Lax-Friedrichs flux and the moist wave-speed bound,
+ *     periodic or slip-wall boundaries (Section 3.2);
+ *   - diagonal mass matrix and the SSPRK(4,3) time step (Section 3.3).
+ * The spatial basis is nodal: tensor-product Gauss-Lobatto points on
+ * structured boxes, which double as quadrature points (lumped, diagonal
+ * mass); the L2 projection of Section 3.4 is then the identity.
+ *
+ * Memory and ownership
+ *   All state arrays passed to the hot calls are DEVICE pointers owned by the
+ *   caller.  The library never frees them.  The handle owns tables, background
+ *   profiles, stage buffers and status words; these are allocated in
+ *   dg_create / dg_create_batch and released in dg_destroy.  Hot calls
+ *   (dg_rhs, dg_saturation_split, dg_rk_step, the *_vjp calls) allocate
+ *   nothing and only enqueue work on the given stream.  Calls on one handle
+ *   must not overlap in time (they share the handle's stage buffers).
+ *
+ * Layout
+ *   U is structure-of-arrays U[v][e][n]: variable v in the order above,
+ *   element e = ex + nx (ey + ny ez) (2D: e = ex + nx ez; the last axis is
+ *   vertical), node n = i + (k+1) (j + (k+1) l) with i along x.  dtype is
+ *   double (DG_FP64) or float (DG_FP32_BULK).  For a batch the members'
+ *   elements are concatenated: member m owns elements
+ *   [dg_member_offset(m), dg_member_offset(m) + ne_m) of every variable.
+ *   Background arrays are per vertical node index iz = ez (k+1) + l.
+ *
+ * Errors
+ *   Every call returns a dg_status; DG_OK is 0.  On any other status
+ *   dg_last_error() returns a message (thread-local).  Argument errors are
+ *   reported before anything is enqueued.  Problems found on the device
+ *   (a Newton solve that did not converge, non-finite values, a state with no
+ *   temperature above 50 K) never abort: they set status words that
+ *   dg_get_stats reads.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_handle dg_handle;
+
+typedef enum {
+  DG_OK = 0,
+  DG_EINVAL = -1,        /* bad argument (sizes, orders, pointers)            */
+  DG_ENOMEM = -2,        /* device allocation failed in dg_create*            */
+  DG_EHIP = -3,          /* a HIP runtime call failed                          */
+  DG_ENOCONV = -4,       /* dg_get_stats: some Newton solve did not converge  */
+  DG_ENONFINITE = -5,    /* dg_get_stats: non-finite or invalid state seen    */
+  DG_EUNSUPPORTED = -6   /* valid request this build does not implement       */
+} dg_status;
+
+enum { DG_PERIODIC = 0, DG_SLIPWALL = 1 };       /* boundary type per axis     */
+enum { DG_FP64 = 0, DG_FP32_BULK = 1 };          /* precision of U and flux    */
+enum { DG_SSPRK43 = 0, DG_SSPRK33 = 1 };          /* time integrator           */
+enum { DG_VR_CONST = 0, DG_VR_COSMO = 1 };       /* terminal rain speed model  */
+
+/* Structured box mesh; axis dim-1 is vertical (gravity along -e_z).  bc[a]
+ * applies to both ends of axis a. */
+typedef struct {
+  int dim;            /* 2 or 3                                  */
+  int n[3];           /* elements per axis (n[a] >= 1)           */
+  double lo[3], hi[3];
+  int bc[3];          /* DG_PERIODIC or DG_SLIPWALL              */
+} dg_mesh;
+
+/* Model parameters.  Thermodynamic constants: the paper's appendix table;
+ * g is not in the table (9.81).  Kessler/COSMO rain closure: Section 2.1. */
+typedef struct {
+  double g, cvd, cvv, cl, cpd, cpv, Rd, Rv, Lref, Tref, eref, pref;
+  int rain;                   /* 0: nvars = 3 + dim; 1: nvars = 4 + dim       */
+  int vr_mode;                /* DG_VR_CONST or DG_VR_COSMO                    */
+  double vr_const;            /* m/s, for DG_VR_CONST                          */
+  double rho_w, N0r, v0r;     /* COSMO terminal-speed parameters               */
+  double q_au;                /* autoconversion threshold (0 in the paper)     */
+  int precision;              /* DG_FP64 or DG_FP32_BULK                       */
+  int rk;                     /* DG_SSPRK43 (default) or DG_SSPRK33            */
+  double newton_rtol;         /* split stops when |dT| <= rtol * T (1e-14)     */
+  int newton_maxit;           /* iteration cap (30); counted as non-converged  */
+} dg_params;
+
+typedef struct {
+  long long splits;           /* node splits performed since the last reset    */
+  long long nonconverged;     /* splits that hit newton_maxit                  */
+  int max_iters;              /* largest Newton iteration count seen           */
+  int nonfinite;              /* 1 if a non-finite or invalid state was seen   */
+} dg_stats;
+
+/* Fill *p with the paper's constants, no rain, FP64, SSPRK(4,3). */
+void dg_default_params(dg_params* p);
+
+/* Create a handle for one mesh.  order k in 1..4, nvars = 3 + dim (rain = 0)
+ * or 4 + dim (rain = 1), otherwise DG_EINVAL.  *out receives the handle. */
+dg_status dg_create(const dg_mesh* mesh, int order, int nvars, const dg_params* p,
+                    dg_handle** out);
+
+/* Create a handle for an ensemble of nmembers meshes of the same order,
+ * dimension and variable set; each member advances with its own dt. */
+dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int order, int nvars,
+                          const dg_params* p, dg_handle** out);
+
+/* Background state of member m (Section 2.3): HOST arrays of n_z (k+1)
+ * doubles at the node heights.  rho_r may be NULL (taken as 0).  The
+ * background pressure is computed on the device as the equation of state of
+ * the split background state.  Must be called for every member before the
+ * first hot call; synchronises the device. */
+dg_status dg_set_background(dg_handle* h, int member, const double* rho_d,
+                            const double* rho_m, const double* rho_r, const double* E);
+
+/* Element offset and element count of member m in the concatenated layout. */
+dg_status dg_member_offset(const dg_handle* h, int member, long long* elem_offset,
+                           long long* nelem);
+
+/* Total number of values in one state array (nvars x elements x nodes). */
+long long dg_state_size(const dg_handle* h);
+
+/* dUdt = M^{-1} (volume + face + source terms) of Section 3.2, including the
+ * pointwise split of Section 3.4.  U and dUdt: device arrays in the state
+ * layout and precision; they must not alias. */
+dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t stream);
+
+/* Implicit condensation split of Section 2.2 at every node: device double
+ * arrays of one value per node (elements x nodes).  T is in/out: if
+ * use_guess != 0 its contents seed Newton (warm start), otherwise it is
+ * output only.  rho_v or rho_c may be NULL. */
+dg_status dg_saturation_split(dg_handle* h, const void* U, double* T, int use_guess,
+                              double* rho_v, double* rho_c, hipStream_t stream);
+
+/* nsteps SSP-RK steps in place on U.  dt: HOST array of 1 value (single mesh)
+ * or nmembers values (batch). */
+dg_status dg_rk_step(dg_handle* h, void* U, const double* dt, int nsteps, hipStream_t stream);
+
+/* Vector-Jacobian product of dg_rhs: U_bar = (d rhs / d U)^T dUdt_bar, with the
+ * implicit-function derivative of the split.  Arrays in the state layout and
+ * precision; U_bar is overwritten. */
+dg_status dg_rhs_vjp(dg_handle* h, const void* U, const void* dUdt_bar, void* U_bar,
+                     hipStream_t stream);
+
+/* Vector-Jacobian product of the split: U_bar = (d(T, rho_v, rho_c)/dU)^T
+ * (T_bar, rho_v_bar, rho_c_bar).  The bar arrays are device doubles per node
+ * (any may be NULL); U_bar is overwritten. */
+dg_status dg_saturation_split_vjp(dg_handle* h, const void* U, const double* T_bar,
+                                  const double* rho_v_bar, const double* rho_c_bar,
+                                  void* U_bar, hipStream_t stream);
+
+/* Vector-Jacobian product of one RK step: U_n_bar = (d U_{n+1}/d U_n)^T
+ * U_np1_bar.  The stages are recomputed from U_n.  dt as in dg_rk_step. */
+dg_status dg_rk_step_vjp(dg_handle* h, const void* U_n, const void* U_np1_bar, void* U_n_bar,
+                         const double* dt, hipStream_t stream);
+
+/* Conservation diagnostics of member m (or of all members if m < 0), in FP64
+ * with a fixed-order reduction: out3[0] = sum w J rho_d', out3[1] = sum w J
+ * (rho_m' + rho_r'), out3[2] = instantaneous rain mass flux out through the
+ * slip walls.  out3 is a HOST array; the call synchronises the stream. */
+dg_status dg_reduce_mass(dg_handle* h, int member, const void* U, double* out3,
+                         hipStream_t stream);
+
+/* Read the device status words (synchronises the device).  Returns DG_OK,
+ * DG_ENOCONV or DG_ENONFINITE. */
+dg_status dg_get_stats(dg_handle* h, dg_stats* out);
+dg_status dg_reset_stats(dg_handle* h);
+
+dg_status dg_destroy(dg_handle* h);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

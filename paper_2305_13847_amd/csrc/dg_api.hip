@@ -1,0 +1,505 @@
+// Host side of libdgmoist: the C interface declared in include/dg.h.
+//
+// Validation, Lobatto tables, member/work-item tables, device buffers and the
+// sequencing of kernels on the caller's stream.  Every step of the method runs
+// in the kernels of dg_kernels.h / dg_vjp.h; the host only prepares tables and
+// enqueues work.
+#include <hip/hip_runtime.h>
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/dg.h"
+#include "dg_launch.h"
+
+using namespace dgm;
+
+namespace dgm {
+extern template struct Launch<double>;
+extern template struct Launch<float>;
+}
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_err;
+
+static dg_status fail(dg_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(DG_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));        \
+  } while (0)
+
+extern "C" const char* dg_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct dg_handle {
+  int dim = 0, order = 0, nvars = 0, rain = 0, prec = 0, rk = 0, nmembers = 0;
+  dg_params P{};
+  std::vector<MemberDesc> mem;
+  std::vector<int2> items;
+  std::vector<int> item_off;     // first item of each member (+ total)
+  std::vector<int> hoff;         // first background index of each member (+ total)
+  std::vector<char> bg_set;
+  long long etot = 0, nnodes = 0;
+  int np = 0;
+  size_t state_bytes = 0;
+  // device
+  MemberDesc* mem_d = nullptr;
+  int2* items_d = nullptr;
+  double* bg_d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // rd, rm, rr, E, p
+  void* stage[2] = {nullptr, nullptr};
+  void* stage_x[4] = {nullptr, nullptr, nullptr, nullptr};          // adjoint workspace
+  double* auxT = nullptr;
+  double* auxS = nullptr;
+  double* auxT2 = nullptr;
+  double* auxS2 = nullptr;
+  double* dt_d = nullptr;
+  double* dt_h = nullptr;        // pinned staging for dt
+  double* partial = nullptr;
+  double* red_out = nullptr;
+  unsigned* stats = nullptr;
+  KArgs ka{};
+};
+
+extern "C" void dg_default_params(dg_params* p) {
+  std::memset(p, 0, sizeof *p);
+  // thermodynamic table of the paper's appendix; g is the usual 9.81
+  p->cl = 4218.0; p->cpd = 1005.0; p->cpv = 1850.0; p->cvd = 718.0; p->cvv = 1390.0;
+  p->eref = 610.7; p->Lref = 2.835e6; p->Rd = 287.05; p->Rv = 461.51; p->Tref = 273.15;
+  p->pref = 1.0e5; p->g = 9.81;
+  p->rain = 0; p->vr_mode = DG_VR_CONST; p->vr_const = 5.0;
+  // COSMO warm-rain parameters (Section 2.1)
+  p->rho_w = 1000.0; p->N0r = 8.0e6; p->v0r = 130.0; p->q_au = 0.0;
+  p->precision = DG_FP64; p->rk = DG_SSPRK43;
+  p->newton_rtol = 1e-14; p->newton_maxit = 30;
+}
+
+// Lobatto nodes in closed form (k <= 4), weights 2 / (k (k+1) P_k(x)^2) and the
+// classical Legendre form of the collocation derivative matrix.
+static double legendre_P(int k, double x) {
+  double p0 = 1.0, p1 = x;
+  if (k == 0) return 1.0;
+  for (int m = 1; m < k; ++m) {
+    double p2 = ((2 * m + 1) * x * p1 - m * p0) / (m + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+static void lobatto_tables(int k, double* w, double* Dhat) {
+  double x[kMaxP1];
+  switch (k) {
+    case 1: x[0] = -1; x[1] = 1; break;
+    case 2: x[0] = -1; x[1] = 0; x[2] = 1; break;
+    case 3: x[0] = -1; x[1] = -1 / std::sqrt(5.0); x[2] = -x[1]; x[3] = 1; break;
+    default: x[0] = -1; x[1] = -std::sqrt(3.0 / 7.0); x[2] = 0; x[3] = -x[1]; x[4] = 1; break;
+  }
+  const int p1 = k + 1;
+  double P[kMaxP1];
+  for (int i = 0; i < p1; ++i) {
+    P[i] = legendre_P(k, x[i]);
+    w[i] = 2.0 / (k * (k + 1.0) * P[i] * P[i]);
+  }
+  double Dm[kMaxP1][kMaxP1];   // Dm[a][i] = l_i'(x_a)
+  for (int a = 0; a < p1; ++a)
+    for (int i = 0; i < p1; ++i) {
+      if (a != i) Dm[a][i] = P[a] / (P[i] * (x[a] - x[i]));
+      else if (a == 0) Dm[a][i] = -k * (k + 1.0) / 4.0;
+      else if (a == k) Dm[a][i] = k * (k + 1.0) / 4.0;
+      else Dm[a][i] = 0.0;
+    }
+  for (int i = 0; i < p1; ++i)
+    for (int a = 0; a < p1; ++a) Dhat[i * p1 + a] = w[a] * Dm[a][i] / w[i];
+}
+
+static void free_all(dg_handle* h) {
+  auto F = [](void* p) { if (p) (void)hipFree(p); };
+  F(h->mem_d); F(h->items_d);
+  for (auto& b : h->bg_d) F(b);
+  for (auto& b : h->stage) F(b);
+  for (auto& b : h->stage_x) F(b);
+  F(h->auxT); F(h->auxS); F(h->auxT2); F(h->auxS2);
+  F(h->dt_d); F(h->partial); F(h->red_out); F(h->stats);
+  if (h->dt_h) (void)hipHostFree(h->dt_h);
+}
+
+static dg_status validate_mesh(const dg_mesh* m, int dim) {
+  if (m->dim != dim) return fail(DG_EINVAL, "all members must have the same dimension");
+  for (int a = 0; a < dim; ++a) {
+    if (m->n[a] < 1 || m->n[a] > (1 << 20)) return fail(DG_EINVAL, "mesh.n[%d] = %d out of range", a, m->n[a]);
+    if (!(m->hi[a] > m->lo[a])) return fail(DG_EINVAL, "mesh.hi[%d] must exceed mesh.lo[%d]", a, a);
+    if (m->bc[a] != DG_PERIODIC && m->bc[a] != DG_SLIPWALL)
+      return fail(DG_EINVAL, "mesh.bc[%d] must be DG_PERIODIC or DG_SLIPWALL", a);
+  }
+  return DG_OK;
+}
+
+extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int order, int nvars,
+                                     const dg_params* p, dg_handle** out) {
+  if (!meshes || !p || !out) return fail(DG_EINVAL, "null argument");
+  *out = nullptr;
+  if (nmembers < 1) return fail(DG_EINVAL, "nmembers must be >= 1");
+  const int dim = meshes[0].dim;
+  if (dim != 2 && dim != 3) return fail(DG_EINVAL, "dim must be 2 or 3 (got %d)", dim);
+  if (order < 1 || order > kMaxOrder) return fail(DG_EINVAL, "order must be in 1..%d (got %d)", kMaxOrder, order);
+  if (p->rain != 0 && p->rain != 1) return fail(DG_EINVAL, "rain must be 0 or 1");
+  if (nvars != (p->rain ? 4 : 3) + dim)
+    return fail(DG_EINVAL, "nvars must be %d for dim=%d rain=%d (got %d)", (p->rain ? 4 : 3) + dim, dim, p->rain, nvars);
+  if (p->precision != DG_FP64 && p->precision != DG_FP32_BULK) return fail(DG_EINVAL, "bad precision");
+  if (p->rk != DG_SSPRK43 && p->rk != DG_SSPRK33) return fail(DG_EINVAL, "bad rk scheme");
+  if (p->vr_mode != DG_VR_CONST && p->vr_mode != DG_VR_COSMO) return fail(DG_EINVAL, "bad vr_mode");
+  if (!(p->newton_rtol > 0) || p->newton_maxit < 1) return fail(DG_EINVAL, "bad Newton settings");
+  for (int m = 0; m < nmembers; ++m) {
+    dg_status s = validate_mesh(&meshes[m], dim);
+    if (s != DG_OK) return s;
+  }
+  dg_handle* h = new dg_handle();
+  h->dim = dim; h->order = order; h->nvars = nvars; h->rain = p->rain;
+  h->prec = p->precision; h->rk = p->rk; h->nmembers = nmembers; h->P = *p;
+  const int p1 = order + 1;
+  h->np = dim == 2 ? p1 * p1 : p1 * p1 * p1;
+  const int epb = elems_per_block(order, dim);
+  long long eoff = 0;
+  int hoff = 0;
+  for (int m = 0; m < nmembers; ++m) {
+    const dg_mesh& g = meshes[m];
+    MemberDesc md{};
+    long long ne = 1;
+    md.J = 1.0;
+    for (int a = 0; a < 3; ++a) {
+      md.n[a] = a < dim ? g.n[a] : 1;
+      md.bc[a] = a < dim ? g.bc[a] : 0;
+      const double hh = a < dim ? (g.hi[a] - g.lo[a]) / g.n[a] : 2.0;
+      md.two_over_h[a] = 2.0 / hh;
+      if (a < dim) { ne *= g.n[a]; md.J *= 0.5 * hh; }
+    }
+    for (int a = 0; a < dim; ++a) {
+      md.face_J[a] = 1.0;
+      for (int b = 0; b < dim; ++b)
+        if (b != a) md.face_J[a] *= 0.5 * (g.hi[b] - g.lo[b]) / g.n[b];
+    }
+    if (ne > (1LL << 30)) { delete h; return fail(DG_EINVAL, "member %d too large", m); }
+    md.ne = (int)ne;
+    md.eoff = eoff;
+    md.hoff = hoff;
+    h->item_off.push_back((int)h->items.size());
+    for (int e0 = 0; e0 < md.ne; e0 += epb) h->items.push_back(make_int2(m, e0));
+    h->hoff.push_back(hoff);
+    eoff += ne;
+    hoff += md.n[dim - 1] * p1;
+    h->mem.push_back(md);
+  }
+  h->item_off.push_back((int)h->items.size());
+  h->hoff.push_back(hoff);
+  h->bg_set.assign(nmembers, 0);
+  h->etot = eoff;
+  h->nnodes = eoff * h->np;
+  const size_t rsz = h->prec == DG_FP64 ? sizeof(double) : sizeof(float);
+  h->state_bytes = (size_t)nvars * h->nnodes * rsz;
+
+  // device buffers
+  auto A = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, bytes) == hipSuccess; };
+  bool ok = true;
+  ok = ok && A((void**)&h->mem_d, sizeof(MemberDesc) * nmembers);
+  ok = ok && A((void**)&h->items_d, sizeof(int2) * h->items.size());
+  for (auto& b : h->bg_d) ok = ok && A((void**)&b, sizeof(double) * hoff);
+  for (auto& b : h->stage) ok = ok && A(&b, h->state_bytes);
+  ok = ok && A((void**)&h->auxT, sizeof(double) * h->nnodes);
+  ok = ok && A((void**)&h->auxS, sizeof(double) * h->nnodes);
+  ok = ok && A((void**)&h->dt_d, sizeof(double) * nmembers);
+  ok = ok && A((void**)&h->partial, sizeof(double) * 3 * h->items.size());
+  ok = ok && A((void**)&h->red_out, sizeof(double) * 4);
+  ok = ok && A((void**)&h->stats, sizeof(unsigned) * 8);
+  ok = ok && hipHostMalloc((void**)&h->dt_h, sizeof(double) * nmembers) == hipSuccess;
+  if (!ok) {
+    const size_t sb = h->state_bytes;
+    free_all(h);
+    delete h;
+    return fail(DG_ENOMEM, "device allocation failed (state of %zu bytes)", sb);
+  }
+  if (hipMemcpy(h->mem_d, h->mem.data(), sizeof(MemberDesc) * nmembers, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->items_d, h->items.data(), sizeof(int2) * h->items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->stats, 0, sizeof(unsigned) * 8) != hipSuccess ||
+      hipMemset(h->auxT, 0, sizeof(double) * h->nnodes) != hipSuccess ||
+      hipMemset(h->auxS, 0, sizeof(double) * h->nnodes) != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(DG_EHIP, "initial upload failed");
+  }
+  for (auto& b : h->bg_d) (void)hipMemset(b, 0, sizeof(double) * hoff);
+
+  // kernel argument block
+  KArgs& a = h->ka;
+  a.g = p->g; a.cvd = p->cvd; a.cvv = p->cvv; a.cl = p->cl; a.Rd = p->Rd; a.Rv = p->Rv;
+  a.Tref = p->Tref;
+  a.Lp = p->Lref - p->Rv * p->Tref;
+  const double aa = (p->cpv - p->cl) / p->Rv;
+  a.am1 = aa - 1.0;
+  a.b = (p->Lref - (p->cpv - p->cl) * p->Tref) / p->Rv;
+  a.inv_Tref = 1.0 / p->Tref;
+  a.C0 = p->eref / (p->Rv * p->Tref);
+  a.vr_const = p->vr_const;
+  a.vr_pref = std::pow(M_PI * p->rho_w * p->N0r, -0.125) * p->v0r * std::tgamma(4.5) / 6.0;
+  a.q_au = p->q_au;
+  a.rain = p->rain; a.vr_mode = p->vr_mode;
+  a.rtol = p->newton_rtol; a.maxit = p->newton_maxit;
+  lobatto_tables(order, a.w, a.Dhat);
+  a.mem = h->mem_d;
+  a.items = h->items_d;
+  a.nitems = (int)h->items.size();
+  a.nmembers = nmembers;
+  a.etot = h->etot;
+  a.bg_rd = h->bg_d[0]; a.bg_rm = h->bg_d[1]; a.bg_rr = h->bg_d[2]; a.bg_E = h->bg_d[3];
+  a.bg_p = h->bg_d[4];
+  a.stats = h->stats;
+  *out = h;
+  return DG_OK;
+}
+
+extern "C" dg_status dg_create(const dg_mesh* mesh, int order, int nvars, const dg_params* p,
+                               dg_handle** out) {
+  return dg_create_batch(mesh, 1, order, nvars, p, out);
+}
+
+extern "C" dg_status dg_destroy(dg_handle* h) {
+  if (!h) return DG_OK;
+  (void)hipDeviceSynchronize();
+  free_all(h);
+  delete h;
+  return DG_OK;
+}
+
+extern "C" long long dg_state_size(const dg_handle* h) { return h ? (long long)h->nvars * h->nnodes : 0; }
+
+extern "C" dg_status dg_member_offset(const dg_handle* h, int member, long long* eoff, long long* ne) {
+  if (!h || member < 0 || member >= h->nmembers) return fail(DG_EINVAL, "bad member index");
+  if (eoff) *eoff = h->mem[member].eoff;
+  if (ne) *ne = h->mem[member].ne;
+  return DG_OK;
+}
+
+// background pressure: equation of state of the split background (FP64)
+__global__ void bg_pressure_kernel(KArgs a, int i0, int n, int rain) {
+  const int i = i0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= i0 + n) return;
+  const double rd = a.bg_rd[i], rm = a.bg_rm[i], rr = rain ? a.bg_rr[i] : 0.0;
+  const SplitOut s = split_point(a, rd, rm, rr, a.bg_E[i], 0.0);
+  const double rv = fmin(s.rvs, rm);
+  const_cast<double*>(a.bg_p)[i] = (rd * a.Rd + rv * a.Rv) * s.T;
+}
+
+extern "C" dg_status dg_set_background(dg_handle* h, int member, const double* rd, const double* rm,
+                                       const double* rr, const double* E) {
+  if (!h) return fail(DG_EINVAL, "null handle");
+  if (member < 0 || member >= h->nmembers) return fail(DG_EINVAL, "bad member index %d", member);
+  if (!rd || !rm || !E) return fail(DG_EINVAL, "null background array");
+  const int off = h->hoff[member];
+  const int n = h->hoff[member + 1] - off;
+  std::vector<double> z(n, 0.0);
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(rd[i]) || !std::isfinite(rm[i]) || !std::isfinite(E[i]) || (rr && !std::isfinite(rr[i])))
+      return fail(DG_EINVAL, "non-finite background value at index %d", i);
+  HIP_TRY(hipMemcpy(h->bg_d[0] + off, rd, n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->bg_d[1] + off, rm, n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->bg_d[2] + off, rr ? rr : z.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->bg_d[3] + off, E, n * sizeof(double), hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(bg_pressure_kernel, dim3((n + 127) / 128), dim3(128), 0, 0, h->ka, off, n, h->rain);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipDeviceSynchronize());
+  h->bg_set[member] = 1;
+  return DG_OK;
+}
+
+static dg_status ready(dg_handle* h) {
+  if (!h) return fail(DG_EINVAL, "null handle");
+  for (int m = 0; m < h->nmembers; ++m)
+    if (!h->bg_set[m]) return fail(DG_EINVAL, "background of member %d not set", m);
+  return DG_OK;
+}
+
+static bool do_split(dg_handle* h, const void* U, const double* guess, double* oT, double* o1,
+                     double* o2, int api, hipStream_t s) {
+  const int n = (int)h->items.size();
+  if (h->prec == DG_FP64)
+    return Launch<double>::split(h->ka, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
+  return Launch<float>::split(h->ka, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
+}
+
+static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, const double* aS, void* out,
+                   const void* U0, double c0, double c1, double c2, hipStream_t s) {
+  if (h->prec == DG_FP64)
+    return Launch<double>::rhs(h->ka, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1, c2, s);
+  return Launch<float>::rhs(h->ka, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1, c2, s);
+}
+
+extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t s) {
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !dUdt) return fail(DG_EINVAL, "null state pointer");
+  if (U == dUdt) return fail(DG_EINVAL, "U and dUdt must not alias");
+  if (!do_split(h, U, nullptr, h->auxT, h->auxS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
+  do_rhs(h, 0, U, h->auxT, h->auxS, dUdt, nullptr, 0, 0, 0, s);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+extern "C" dg_status dg_saturation_split(dg_handle* h, const void* U, double* T, int use_guess,
+                                         double* rho_v, double* rho_c, hipStream_t s) {
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !T) return fail(DG_EINVAL, "null pointer");
+  if (!do_split(h, U, use_guess ? T : nullptr, T, rho_v, rho_c, 1, s))
+    return fail(DG_EUNSUPPORTED, "no kernel for this shape");
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+// Shu-Osher coefficients (c0, c1, c2) of out = c0 u0 + c1 u + c2 dt L(u)
+struct Stage { double c0, c1, c2; };
+static const Stage kSSP43[4] = {{0, 1, 0.5}, {0, 1, 0.5}, {2.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}, {0, 1, 0.5}};
+static const Stage kSSP33[3] = {{0, 1, 1}, {0.75, 0.25, 0.25}, {1.0 / 3.0, 2.0 / 3.0, 2.0 / 3.0}};
+
+static dg_status upload_dt(dg_handle* h, const double* dt, hipStream_t s) {
+  for (int m = 0; m < h->nmembers; ++m) {
+    if (!std::isfinite(dt[m]) || !(dt[m] > 0)) return fail(DG_EINVAL, "dt[%d] must be positive and finite", m);
+    h->dt_h[m] = dt[m];
+  }
+  HIP_TRY(hipMemcpyAsync(h->dt_d, h->dt_h, sizeof(double) * h->nmembers, hipMemcpyHostToDevice, s));
+  return DG_OK;
+}
+
+// One RK step in place on U; stage states go to the handle's buffers.  The
+// split of each stage state is warm-started from the previous one.
+static dg_status rk_one(dg_handle* h, void* U, bool first, hipStream_t s) {
+  void* B1 = h->stage[0];
+  void* B2 = h->stage[1];
+  if (h->rk == DG_SSPRK43) {
+    const void* in[4] = {U, B1, B2, B1};
+    void* outp[4] = {B1, B2, B1, U};
+    for (int st = 0; st < 4; ++st) {
+      do_split(h, in[st], (first && st == 0) ? nullptr : h->auxT, h->auxT, h->auxS, nullptr, 0, s);
+      const Stage& c = kSSP43[st];
+      do_rhs(h, 1, in[st], h->auxT, h->auxS, outp[st], U, c.c0, c.c1, c.c2, s);
+    }
+  } else {
+    const void* in[3] = {U, B1, B2};
+    void* outp[3] = {B1, B2, U};
+    for (int st = 0; st < 3; ++st) {
+      do_split(h, in[st], (first && st == 0) ? nullptr : h->auxT, h->auxT, h->auxS, nullptr, 0, s);
+      const Stage& c = kSSP33[st];
+      do_rhs(h, 1, in[st], h->auxT, h->auxS, outp[st], U, c.c0, c.c1, c.c2, s);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+extern "C" dg_status dg_rk_step(dg_handle* h, void* U, const double* dt, int nsteps, hipStream_t s) {
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !dt) return fail(DG_EINVAL, "null pointer");
+  if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
+  st = upload_dt(h, dt, s);
+  if (st != DG_OK) return st;
+  for (int i = 0; i < nsteps; ++i) {
+    st = rk_one(h, U, i == 0, s);
+    if (st != DG_OK) return st;
+  }
+  return DG_OK;
+}
+
+// fixed-order sum of the per-block partials (one block)
+__global__ void reduce_partials_kernel(const double* partial, int n, double* out) {
+  __shared__ double sm[3][256];
+  const int t = threadIdx.x;
+  double acc[3] = {0, 0, 0};
+  for (int i = t; i < n; i += 256)
+    for (int c = 0; c < 3; ++c) acc[c] += partial[3 * i + c];
+  for (int c = 0; c < 3; ++c) sm[c][t] = acc[c];
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (t < st)
+      for (int c = 0; c < 3; ++c) sm[c][t] += sm[c][t + st];
+    __syncthreads();
+  }
+  if (t == 0)
+    for (int c = 0; c < 3; ++c) out[c] = sm[c][0];
+}
+
+extern "C" dg_status dg_reduce_mass(dg_handle* h, int member, const void* U, double* out3, hipStream_t s) {
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !out3) return fail(DG_EINVAL, "null pointer");
+  if (member >= h->nmembers) return fail(DG_EINVAL, "bad member index");
+  const int i0 = member < 0 ? 0 : h->item_off[member];
+  const int i1 = member < 0 ? (int)h->items.size() : h->item_off[member + 1];
+  const int n = i1 - i0;
+  if (h->prec == DG_FP64)
+    Launch<double>::mass(h->ka, h->order, h->dim, h->rain, i0, n, U, h->partial, s);
+  else
+    Launch<float>::mass(h->ka, h->order, h->dim, h->rain, i0, n, U, h->partial, s);
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, h->partial, n, h->red_out);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out3, h->red_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return DG_OK;
+}
+
+extern "C" dg_status dg_get_stats(dg_handle* h, dg_stats* out) {
+  if (!h || !out) return fail(DG_EINVAL, "null pointer");
+  unsigned w[8];
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(w, h->stats, sizeof w, hipMemcpyDeviceToHost));
+  out->max_iters = (int)w[0];
+  out->nonconverged = w[1];
+  out->nonfinite = w[2] ? 1 : 0;
+  unsigned long long cnt;
+  std::memcpy(&cnt, &w[4], sizeof cnt);
+  out->splits = (long long)cnt;
+  if (out->nonfinite) return fail(DG_ENONFINITE, "a state with no valid temperature was seen");
+  if (out->nonconverged) return fail(DG_ENOCONV, "%lld Newton solves hit the iteration cap", out->nonconverged);
+  return DG_OK;
+}
+
+extern "C" dg_status dg_reset_stats(dg_handle* h) {
+  if (!h) return fail(DG_EINVAL, "null handle");
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemset(h->stats, 0, sizeof(unsigned) * 8));
+  return DG_OK;
+}
+
+extern "C" dg_status dg_rhs_vjp(dg_handle* h, const void* U, const void* lam, void* Ub, hipStream_t s) {
+  (void)h; (void)U; (void)lam; (void)Ub; (void)s;
+  return fail(DG_EUNSUPPORTED, "dg_rhs_vjp not available in this build");
+}
+
+extern "C" dg_status dg_saturation_split_vjp(dg_handle* h, const void* U, const double* Tb, const double* rvb,
+                                             const double* rcb, void* Ub, hipStream_t s) {
+  (void)h; (void)U; (void)Tb; (void)rvb; (void)rcb; (void)Ub; (void)s;
+  return fail(DG_EUNSUPPORTED, "dg_saturation_split_vjp not available in this build");
+}
+
+extern "C" dg_status dg_rk_step_vjp(dg_handle* h, const void* Un, const void* Ub1, void* Ub0, const double* dt,
+                                    hipStream_t s) {
+  (void)h; (void)Un; (void)Ub1; (void)Ub0; (void)dt; (void)s;
+  return fail(DG_EUNSUPPORTED, "dg_rk_step_vjp not available in this build");
+}

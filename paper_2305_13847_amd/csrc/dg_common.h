@@ -1,0 +1,55 @@
+// Shared host/device definitions of libdgmoist: kernel argument blocks and the
+// per-member mesh descriptors of a (possibly batched) handle.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgm {
+
+constexpr int kMaxOrder = 4;
+constexpr int kMaxP1 = kMaxOrder + 1;
+
+// One ensemble member: a structured box.  Elements of all members are
+// concatenated; eoff is this member's first global element.
+struct MemberDesc {
+  int n[3];             // elements per axis (n[2] = 1 in 2D)
+  int bc[3];            // 0 periodic, 1 slip wall
+  double two_over_h[3]; // 2 / h_j
+  double J;             // element Jacobian prod_j h_j / 2
+  double face_J[3];     // face Jacobian for a face normal to axis j
+  long long eoff;       // first global element
+  int ne;               // elements of this member
+  int hoff;             // first background index (n_z (k+1) entries)
+};
+
+// Everything the kernels need besides the state arrays.
+struct KArgs {
+  // thermodynamics (Section 2; appendix table)
+  double g, cvd, cvv, cl, Rd, Rv, Tref;
+  double Lp;                       // L_ref - R_v T_ref
+  double am1, b, inv_Tref, C0;     // rho_vs(T) = C0 exp(am1 ln(T/T_ref) + b (1/T_ref - 1/T))
+  double vr_const, vr_pref, q_au;  // terminal speed, COSMO prefactor, autoconversion threshold
+  int rain, vr_mode;
+  double rtol;
+  int maxit;
+  // Lobatto tables: Dhat[i*(k+1)+a] = w_a D_ai / w_i, weights w
+  double Dhat[kMaxP1 * kMaxP1];
+  double w[kMaxP1];
+  // members and work items (member, first element) of EPB elements each
+  const MemberDesc* mem;
+  const int2* items;
+  int nitems;
+  int nmembers;
+  long long etot;                  // elements of all members (variable stride / np)
+  // background per vertical node index, concatenated over members
+  const double* bg_rd;
+  const double* bg_rm;
+  const double* bg_rr;
+  const double* bg_E;
+  const double* bg_p;
+  // status words: [0] max iterations, [1] non-converged, [2] invalid, [3] spare,
+  // [4..5] split count (64-bit)
+  unsigned* stats;
+};
+
+}  // namespace dgm

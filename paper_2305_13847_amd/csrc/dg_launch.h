@@ -1,0 +1,103 @@
+// Host-side launchers: map runtime (order, dimension, rain) to the kernel
+// instantiations.  Each precision is instantiated in its own translation unit.
+#pragma once
+#include <type_traits>
+#include "dg_kernels.h"
+#include "dg_vjp.h"
+
+namespace dgm {
+
+template <typename F>
+bool dispatch_shape(int K, int D, int rain, F&& f) {
+#define DGM_CASE(k, d, r)                                                         \
+  if (K == k && D == d && rain == r) {                                            \
+    f(std::integral_constant<int, k>{}, std::integral_constant<int, d>{},         \
+      std::integral_constant<int, r>{});                                          \
+    return true;                                                                  \
+  }
+  DGM_CASE(1, 2, 0) DGM_CASE(1, 2, 1) DGM_CASE(1, 3, 0) DGM_CASE(1, 3, 1)
+  DGM_CASE(2, 2, 0) DGM_CASE(2, 2, 1) DGM_CASE(2, 3, 0) DGM_CASE(2, 3, 1)
+  DGM_CASE(3, 2, 0) DGM_CASE(3, 2, 1) DGM_CASE(3, 3, 0) DGM_CASE(3, 3, 1)
+  DGM_CASE(4, 2, 0) DGM_CASE(4, 2, 1) DGM_CASE(4, 3, 0) DGM_CASE(4, 3, 1)
+#undef DGM_CASE
+  return false;
+}
+
+inline int threads_per_block(int K, int D) {
+  int np = (D == 2) ? (K + 1) * (K + 1) : (K + 1) * (K + 1) * (K + 1);
+  int epb = 256 / np > 0 ? 256 / np : 1;
+  return epb * np;
+}
+
+inline int elems_per_block(int K, int D) {
+  int np = (D == 2) ? (K + 1) * (K + 1) : (K + 1) * (K + 1) * (K + 1);
+  return 256 / np > 0 ? 256 / np : 1;
+}
+
+template <typename R>
+struct Launch {
+  // API != 0: write T, rho_v, rho_c; otherwise T and rho_vs(T)
+  static bool split(const KArgs& a, int K, int D, int rain, int item0, int nitems, const void* U,
+                    const double* guess, double* oT, double* o1, double* o2, int api,
+                    hipStream_t s) {
+    if (nitems <= 0) return true;
+    return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
+      constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
+      dim3 grid(nitems), block(Shape<K_, D_>::NT);
+      if (api)
+        hipLaunchKernelGGL((split_kernel<R, K_, D_, R_, 1>), grid, block, 0, s, a, item0,
+                           (const R*)U, guess, oT, o1, o2);
+      else
+        hipLaunchKernelGGL((split_kernel<R, K_, D_, R_, 0>), grid, block, 0, s, a, item0,
+                           (const R*)U, guess, oT, o1, o2);
+    });
+  }
+
+  // mode 0: out = dU/dt; mode 1: out = c0 U0 + c1 U + c2 dt dU/dt
+  static bool rhs(const KArgs& a, int K, int D, int rain, int mode, const void* U,
+                  const double* auxT, const double* auxS, void* out, const void* U0,
+                  const double* dt, double c0, double c1, double c2, hipStream_t s) {
+    return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
+      constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
+      dim3 grid(a.nitems), block(Shape<K_, D_>::NT);
+      if (mode == 0)
+        hipLaunchKernelGGL((rhs_kernel<R, K_, D_, R_, 0>), grid, block, 0, s, a, (const R*)U, auxT,
+                           auxS, (R*)out, (const R*)U0, dt, c0, c1, c2);
+      else
+        hipLaunchKernelGGL((rhs_kernel<R, K_, D_, R_, 1>), grid, block, 0, s, a, (const R*)U, auxT,
+                           auxS, (R*)out, (const R*)U0, dt, c0, c1, c2);
+    });
+  }
+
+  static bool mass(const KArgs& a, int K, int D, int rain, int item0, int nitems, const void* U,
+                   double* partial, hipStream_t s) {
+    return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
+      constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
+      hipLaunchKernelGGL((mass_kernel<R, K_, D_, R_>), dim3(nitems), dim3(Shape<K_, D_>::NT), 0, s,
+                         a, item0, (const R*)U, partial);
+    });
+  }
+
+  // adjoint of the right-hand side (dg_vjp.h)
+  static bool rhs_vjp(const KArgs& a, int K, int D, int rain, const void* U, const double* auxT,
+                      const double* auxS, const void* lam, void* out, hipStream_t s) {
+    return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
+      constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
+      hipLaunchKernelGGL((rhs_vjp_kernel<R, K_, D_, R_>), dim3(a.nitems), dim3(Shape<K_, D_>::NT), 0,
+                         s, a, (const R*)U, auxT, auxS, (const R*)lam, (R*)out);
+    });
+  }
+
+  static bool split_vjp(const KArgs& a, int K, int D, int rain, const void* U, const double* auxT,
+                        const double* auxS, const double* Tb, const double* rvb,
+                        const double* rcb, void* out, hipStream_t s) {
+    return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
+      constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
+      hipLaunchKernelGGL((split_vjp_kernel<R, K_, D_, R_>), dim3(a.nitems),
+                         dim3(Shape<K_, D_>::NT), 0, s, a, (const R*)U, auxT, auxS, Tb, rvb, rcb,
+                         (R*)out);
+    });
+  }
+};
+
+}  // namespace dgm
