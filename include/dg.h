@@ -177,6 +177,16 @@ dg_status dg_reset_stats(dg_handle* h);
 
 dg_status dg_destroy(dg_handle* h);
 
+/* Kernel timing (instrumentation).  While enabled, every kernel the library
+ * launches is bracketed by HIP events on its stream; dg_timing_read
+ * synchronises and returns the accumulated device time and launch count of a
+ * kernel class since it was enabled.  Classes: DG_K_SPLIT (the split),
+ * DG_K_STAGE (right-hand side / fused stage), DG_K_ADJOINT (the *_vjp
+ * kernels), DG_K_OTHER.  Enabling allocates events; not for captured graphs. */
+enum { DG_K_SPLIT = 0, DG_K_STAGE = 1, DG_K_ADJOINT = 2, DG_K_OTHER = 3 };
+dg_status dg_timing_enable(dg_handle* h, int enable);
+dg_status dg_timing_read(dg_handle* h, int kclass, double* total_ms, long long* launches);
+
 /* Message for the last non-OK status returned on this thread. */
 const char* dg_last_error(void);
 

@@ -13,7 +13,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/dg.h"
+#include "dg.h"
 #include "dg_launch.h"
 
 using namespace dgm;
@@ -76,7 +76,47 @@ struct dg_handle {
   double* partial = nullptr;
   double* red_out = nullptr;
   unsigned* stats = nullptr;
+  long long splits = 0;          // node splits enqueued since the last reset
   KArgs ka{};
+  // kernel timing
+  bool timing = false;
+  std::vector<hipEvent_t> ev;        // pairs (start, stop)
+  std::vector<int> ev_class;         // class of each pending pair
+  int ev_used = 0;
+  double t_ms[4] = {0, 0, 0, 0};
+  long long t_n[4] = {0, 0, 0, 0};
+};
+
+static const int kEvPairs = 2048;
+
+static void timing_flush(dg_handle* h) {
+  if (!h->timing || h->ev_used == 0) return;
+  for (int i = 0; i < h->ev_used; ++i) {
+    (void)hipEventSynchronize(h->ev[2 * i + 1]);
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]) == hipSuccess) {
+      h->t_ms[h->ev_class[i]] += ms;
+      h->t_n[h->ev_class[i]] += 1;
+    }
+  }
+  h->ev_used = 0;
+}
+
+// RAII bracket of one kernel launch with timing events
+struct KTimer {
+  dg_handle* h;
+  int slot = -1;
+  hipStream_t s;
+  KTimer(dg_handle* hh, int cls, hipStream_t ss) : h(hh), s(ss) {
+    if (!h->timing) return;
+    if (h->ev_used == kEvPairs) timing_flush(h);
+    slot = h->ev_used++;
+    h->ev_class[slot] = cls;
+    (void)hipEventRecord(h->ev[2 * slot], s);
+  }
+  ~KTimer() {
+    if (slot >= 0) (void)hipEventRecord(h->ev[2 * slot + 1], s);
+  }
 };
 
 extern "C" void dg_default_params(dg_params* p) {
@@ -225,6 +265,8 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   for (auto& b : h->stage) ok = ok && A(&b, h->state_bytes);
   ok = ok && A((void**)&h->auxT, sizeof(double) * h->nnodes);
   ok = ok && A((void**)&h->auxS, sizeof(double) * h->nnodes);
+  ok = ok && A((void**)&h->auxT2, sizeof(double) * h->nnodes);
+  ok = ok && A((void**)&h->auxS2, sizeof(double) * h->nnodes);
   ok = ok && A((void**)&h->dt_d, sizeof(double) * nmembers);
   ok = ok && A((void**)&h->partial, sizeof(double) * 3 * h->items.size());
   ok = ok && A((void**)&h->red_out, sizeof(double) * 4);
@@ -283,6 +325,7 @@ extern "C" dg_status dg_create(const dg_mesh* mesh, int order, int nvars, const 
 extern "C" dg_status dg_destroy(dg_handle* h) {
   if (!h) return DG_OK;
   (void)hipDeviceSynchronize();
+  for (auto e : h->ev) (void)hipEventDestroy(e);
   free_all(h);
   delete h;
   return DG_OK;
@@ -325,6 +368,11 @@ extern "C" dg_status dg_set_background(dg_handle* h, int member, const double* r
   hipLaunchKernelGGL(bg_pressure_kernel, dim3((n + 127) / 128), dim3(128), 0, 0, h->ka, off, n, h->rain);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipDeviceSynchronize());
+  std::vector<double> pb(n);
+  HIP_TRY(hipMemcpy(pb.data(), h->bg_d[4] + off, n * sizeof(double), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i)
+    if (!std::isfinite(pb[i]) || !(pb[i] > 0))
+      return fail(DG_EINVAL, "background state at index %d has no valid temperature", i);
   h->bg_set[member] = 1;
   return DG_OK;
 }
@@ -339,16 +387,23 @@ static dg_status ready(dg_handle* h) {
 static bool do_split(dg_handle* h, const void* U, const double* guess, double* oT, double* o1,
                      double* o2, int api, hipStream_t s) {
   const int n = (int)h->items.size();
+  KTimer kt(h, DG_K_SPLIT, s);
+  h->splits += h->nnodes;
   if (h->prec == DG_FP64)
     return Launch<double>::split(h->ka, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
   return Launch<float>::split(h->ka, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
 }
 
 static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, const double* aS, void* out,
-                   const void* U0, double c0, double c1, double c2, hipStream_t s) {
+                   const void* U0, double c0, double c1, double c2, hipStream_t s,
+                   double* oT = nullptr, double* oS = nullptr, int refresh = 0) {
+  KTimer kt(h, DG_K_STAGE, s);
+  if (mode == 2) h->splits += h->nnodes;
   if (h->prec == DG_FP64)
-    return Launch<double>::rhs(h->ka, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1, c2, s);
-  return Launch<float>::rhs(h->ka, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1, c2, s);
+    return Launch<double>::rhs(h->ka, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1,
+                               c2, oT, oS, refresh, s);
+  return Launch<float>::rhs(h->ka, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1, c2,
+                            oT, oS, refresh, s);
 }
 
 extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t s) {
@@ -387,27 +442,31 @@ static dg_status upload_dt(dg_handle* h, const double* dt, hipStream_t s) {
   return DG_OK;
 }
 
-// One RK step in place on U; stage states go to the handle's buffers.  The
-// split of each stage state is warm-started from the previous one.
-static dg_status rk_one(dg_handle* h, void* U, bool first, hipStream_t s) {
+// One RK step in place on U; stage states go to the handle's buffers.  Each
+// fused stage kernel also splits the state it writes, so the next stage reads
+// (T, rho_vs) from the ping-pong aux buffers; only the first stage of a call
+// runs the stand-alone split.  *cur is the aux buffer holding the split of U.
+static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t s) {
   void* B1 = h->stage[0];
   void* B2 = h->stage[1];
-  if (h->rk == DG_SSPRK43) {
-    const void* in[4] = {U, B1, B2, B1};
-    void* outp[4] = {B1, B2, B1, U};
-    for (int st = 0; st < 4; ++st) {
-      do_split(h, in[st], (first && st == 0) ? nullptr : h->auxT, h->auxT, h->auxS, nullptr, 0, s);
-      const Stage& c = kSSP43[st];
-      do_rhs(h, 1, in[st], h->auxT, h->auxS, outp[st], U, c.c0, c.c1, c.c2, s);
-    }
-  } else {
-    const void* in[3] = {U, B1, B2};
-    void* outp[3] = {B1, B2, U};
-    for (int st = 0; st < 3; ++st) {
-      do_split(h, in[st], (first && st == 0) ? nullptr : h->auxT, h->auxT, h->auxS, nullptr, 0, s);
-      const Stage& c = kSSP33[st];
-      do_rhs(h, 1, in[st], h->auxT, h->auxS, outp[st], U, c.c0, c.c1, c.c2, s);
-    }
+  double* aT[2] = {h->auxT, h->auxT2};
+  double* aS[2] = {h->auxS, h->auxS2};
+  if (first) {
+    *cur = 0;
+    do_split(h, U, nullptr, aT[0], aS[0], nullptr, 0, s);
+  }
+  const int ns = h->rk == DG_SSPRK43 ? 4 : 3;
+  const void* in43[4] = {U, B1, B2, B1};
+  void* out43[4] = {B1, B2, B1, U};
+  const void* in33[3] = {U, B1, B2};
+  void* out33[3] = {B1, B2, U};
+  for (int st = 0; st < ns; ++st) {
+    const Stage& c = h->rk == DG_SSPRK43 ? kSSP43[st] : kSSP33[st];
+    const void* in = h->rk == DG_SSPRK43 ? in43[st] : in33[st];
+    void* outp = h->rk == DG_SSPRK43 ? out43[st] : out33[st];
+    const int a = *cur, b = 1 - *cur;
+    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], st == ns - 1);
+    *cur = b;
   }
   HIP_TRY(hipGetLastError());
   return DG_OK;
@@ -420,8 +479,9 @@ extern "C" dg_status dg_rk_step(dg_handle* h, void* U, const double* dt, int nst
   if (nsteps < 0) return fail(DG_EINVAL, "nsteps must be >= 0");
   st = upload_dt(h, dt, s);
   if (st != DG_OK) return st;
+  int cur = 0;
   for (int i = 0; i < nsteps; ++i) {
-    st = rk_one(h, U, i == 0, s);
+    st = rk_one(h, U, i == 0, &cur, s);
     if (st != DG_OK) return st;
   }
   return DG_OK;
@@ -472,9 +532,7 @@ extern "C" dg_status dg_get_stats(dg_handle* h, dg_stats* out) {
   out->max_iters = (int)w[0];
   out->nonconverged = w[1];
   out->nonfinite = w[2] ? 1 : 0;
-  unsigned long long cnt;
-  std::memcpy(&cnt, &w[4], sizeof cnt);
-  out->splits = (long long)cnt;
+  out->splits = h->splits;
   if (out->nonfinite) return fail(DG_ENONFINITE, "a state with no valid temperature was seen");
   if (out->nonconverged) return fail(DG_ENOCONV, "%lld Newton solves hit the iteration cap", out->nonconverged);
   return DG_OK;
@@ -484,6 +542,7 @@ extern "C" dg_status dg_reset_stats(dg_handle* h) {
   if (!h) return fail(DG_EINVAL, "null handle");
   HIP_TRY(hipDeviceSynchronize());
   HIP_TRY(hipMemset(h->stats, 0, sizeof(unsigned) * 8));
+  h->splits = 0;
   return DG_OK;
 }
 
@@ -502,4 +561,30 @@ extern "C" dg_status dg_rk_step_vjp(dg_handle* h, const void* Un, const void* Ub
                                     hipStream_t s) {
   (void)h; (void)Un; (void)Ub1; (void)Ub0; (void)dt; (void)s;
   return fail(DG_EUNSUPPORTED, "dg_rk_step_vjp not available in this build");
+}
+
+extern "C" dg_status dg_timing_enable(dg_handle* h, int enable) {
+  if (!h) return fail(DG_EINVAL, "null handle");
+  if (enable) {
+    if (h->ev.empty()) {
+      h->ev.resize(2 * kEvPairs);
+      h->ev_class.resize(kEvPairs);
+      for (auto& e : h->ev) HIP_TRY(hipEventCreate(&e));
+    }
+    timing_flush(h);
+    for (int c = 0; c < 4; ++c) { h->t_ms[c] = 0; h->t_n[c] = 0; }
+    h->timing = true;
+  } else {
+    timing_flush(h);
+    h->timing = false;
+  }
+  return DG_OK;
+}
+
+extern "C" dg_status dg_timing_read(dg_handle* h, int kclass, double* total_ms, long long* launches) {
+  if (!h || kclass < 0 || kclass > 3) return fail(DG_EINVAL, "bad handle or class");
+  timing_flush(h);
+  if (total_ms) *total_ms = h->t_ms[kclass];
+  if (launches) *launches = h->t_n[kclass];
+  return DG_OK;
 }

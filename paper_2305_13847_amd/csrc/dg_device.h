@@ -42,62 +42,110 @@ struct SplitOut {
   int bad;      // 1: no valid temperature, 2: iteration cap reached
 };
 
+// rho_vs near an anchor temperature T0 where r0 = rho_vs(T0) is known:
+//   rho_vs(T) = r0 exp(phi(T) - phi(T0)),
+//   phi(T) - phi(T0) = (a - 1) log(1 + x) + b x / (T0 (1 + x)),  x = (T - T0)/T0,
+// with log(1 + x), 1/(1 + x) and exp(.) - 1 summed as Taylor series.  For
+// |x| <= kAnchorX the truncation errors are below 1e-19 relative (|x|^8/8,
+// |x|^8 and |dphi|^11/11! with |dphi| < 0.09 for T0 >= 200 K).
+constexpr double kAnchorX = 2.0e-3;
+
+struct Anchor {
+  double T0, r0, inv0;
+};
+
+__device__ __forceinline__ Anchor make_anchor(const KArgs& a, double T) {
+  Anchor A;
+  A.T0 = T;
+  A.inv0 = 1.0 / T;
+  A.r0 = a.C0 * exp(a.am1 * log(T * a.inv_Tref) + a.b * (a.inv_Tref - A.inv0));
+  return A;
+}
+
+__device__ __forceinline__ bool in_anchor(const Anchor& A, double T) {
+  return fabs(T - A.T0) <= kAnchorX * A.T0;
+}
+
+// rho_vs(T) and d rho_vs / dT from the anchor
+__device__ __forceinline__ double rvs_near(const KArgs& a, const Anchor& A, double T, double* drvs) {
+  const double x = (T - A.T0) * A.inv0;
+  const double l = x * (1.0 + x * (-0.5 + x * (1.0 / 3.0 + x * (-0.25 + x * (0.2 + x * (-1.0 / 6.0 + x * (1.0 / 7.0)))))));
+  const double q = 1.0 + x * (-1.0 + x * (1.0 + x * (-1.0 + x * (1.0 + x * (-1.0 + x * (1.0 - x))))));
+  const double d = a.am1 * l + a.b * A.inv0 * x * q;
+  const double e = d * (1.0 + d * (1.0 / 2 + d * (1.0 / 6 + d * (1.0 / 24 + d * (1.0 / 120 + d * (1.0 / 720 +
+                   d * (1.0 / 5040 + d * (1.0 / 40320 + d * (1.0 / 362880 + d * (1.0 / 3628800))))))))));
+  const double r = A.r0 + A.r0 * e;
+  const double invT = A.inv0 * q;
+  *drvs = r * (a.am1 + a.b * invT) * invT;
+  return r;
+}
+
+// FP64 reciprocal: hardware estimate refined by two Newton steps
+__device__ __forceinline__ double rcp64(double v) {
+  double r = __builtin_amdgcn_rcp(v);
+  r = fma(fma(-v, r, 1.0), r, r);
+  r = fma(fma(-v, r, 1.0), r, r);
+  return r;
+}
+
 // Implicit condensation (Section 2.2): find T with
 //   rho e = (c_vd rd + c_vv rv + c_l (rm - rv + rr)) (T - T_ref) + rv (L_ref - R_v T_ref),
 //   rv = min(rho_vs(T), rm).
-// The all-vapour temperature Tu decides the branch exactly.  On the saturated
-// branch f(T) is increasing and convex, so Newton from any start at or above
-// the root's lower bound converges; iterates are kept above that bound.
-__device__ __forceinline__ SplitOut split_point(const KArgs& a, double rd, double rm, double rr,
-                                                double re, double guess) {
-  SplitOut o;
-  o.iters = 0;
-  o.bad = 0;
-  const double Cu = a.cvd * rd + a.cvv * rm + a.cl * rr;
-  const double Tu = a.Tref + (re - rm * a.Lp) / Cu;
-  if (!isfinite(Tu) || !(Cu > 0.0)) {
-    o.T = Tu; o.rvs = rm; o.bad = 1;
-    return o;
-  }
-  if (Tu > 0.0) {
-    const double r = rho_vs(a, Tu);
-    if (rm <= r) { o.T = Tu; o.rvs = r; return o; }
-  }
+// The map T -> rho e is strictly increasing, so the root is unique.  Each
+// branch gives a candidate and an exact test:
+//   unsaturated: T = Tu (all water as vapour), valid iff rm <= rho_vs(Tu);
+//   saturated:   the root Ts of f(T) = rho e(T, rv = rho_vs(T)) - rho e,
+//                valid iff rho_vs(Ts) <= rm (then Ts is the unique root).
+// `sat_first` names the branch to try first (with a warm start, the branch
+// that held before), so a node normally evaluates one branch.  On the
+// saturated branch f is increasing and convex; Newton evaluates rho_vs by
+// series around an anchor that is re-based when an iterate leaves its range.
+// The Newton step uses the hardware reciprocal of f' (relative error far
+// below the step's own size, so convergence stays quadratic).  Stopping:
+// |dT| <= rtol T, or, above 150 K, the quadratic-convergence bound: after a
+// step dT the error is at most M dT^2 with M = max |f''| / (2 min f') < 1 K^-1,
+// so |dT| <= sqrt(rtol T / M) already leaves an error below rtol T.
+// If `A` holds a valid anchor (A.T0 > 0) it is used and updated in place.
+struct NewtonOut {
+  double T, rvs;
+  int iters;
+  int state;   // 0 converged, 1 root lies below Tu (not saturated), 2 iteration cap
+};
+
+__device__ __forceinline__ NewtonOut newton_sat(const KArgs& a, double Cu, double rm, double re,
+                                                double Tu, double lo, double T, Anchor& A) {
   const double dc = a.cvv - a.cl;
-  double lo = Tu;
-  if (!(Tu > 50.0)) {
-    const double r = rho_vs(a, 50.0);
-    const double f = (Cu + dc * (r - rm)) * (50.0 - a.Tref) + r * a.Lp - re;
-    if (!(f < 0.0)) { o.T = Tu; o.rvs = rm; o.bad = 1; return o; }
-    lo = 50.0;
-  }
-  double T = (guess > lo && guess < 1.0e4) ? guess : lo;
+  if (!(A.T0 > 0.0) || !in_anchor(A, T)) A = make_anchor(a, T);
+  const double tol_lin = a.rtol * T;
+  const double tol = T > 150.0 ? fmax(tol_lin, sqrt(tol_lin)) : tol_lin;
+  NewtonOut o;
+  o.state = 2;
   double rvs = 0.0;
   int it = 0;
-  bool conv = false;
   while (it < a.maxit) {
-    const double inv = 1.0 / T;
-    rvs = a.C0 * exp(a.am1 * log(T * a.inv_Tref) + a.b * (a.inv_Tref - inv));
+    if (!in_anchor(A, T)) A = make_anchor(a, T);
+    double drvs;
+    rvs = rvs_near(a, A, T, &drvs);
     const double Cv = Cu + dc * (rvs - rm);
     const double Tm = T - a.Tref;
     const double f = Cv * Tm + rvs * a.Lp - re;
-    const double drvs = rvs * (a.am1 + a.b * inv) * inv;
     const double fp = Cv + drvs * (dc * Tm + a.Lp);
-    const double dT = -f / fp;
+    const double dT = -f * __builtin_amdgcn_rcp(fp);
     ++it;
-    if (fabs(dT) <= a.rtol * T) {
+    if (fabs(dT) <= tol) {
       T += dT;
-      rvs += drvs * dT;          // first-order update; the step is below rounding
-      conv = true;
+      rvs += drvs * dT;          // first order is exact to rounding for this step size
+      o.state = 0;
       break;
     }
     double Tn = T + dT;
-    if (!(Tn > lo)) Tn = 0.5 * (T + lo);
+    if (!(Tn > lo)) {
+      // f is convex: from the right of the root Newton never overshoots, so a
+      // step below the bound means the saturated root lies below Tu
+      if (f > 0.0 && lo == Tu) { o.state = 1; break; }
+      Tn = 0.5 * (T + lo);
+    }
     T = Tn;
-  }
-  if (!conv) {
-    rvs = rho_vs(a, T);
-    o.bad = 2;
   }
   o.T = T;
   o.rvs = rvs;
@@ -105,30 +153,91 @@ __device__ __forceinline__ SplitOut split_point(const KArgs& a, double rd, doubl
   return o;
 }
 
-// Accumulate split statistics of a whole block into the status words.
-template <int NT>
-__device__ __forceinline__ void record_stats(const KArgs& a, int iters, int bad, bool active) {
-  __shared__ int s_max, s_nc, s_bad, s_cnt;
-  if (threadIdx.x == 0) { s_max = 0; s_nc = 0; s_bad = 0; s_cnt = 0; }
-  __syncthreads();
-  if (active) {
-    if (iters > 0) atomicMax(&s_max, iters);
-    if (bad == 2) atomicAdd(&s_nc, 1);
-    if (bad == 1) atomicOr(&s_bad, 1);
-    atomicAdd(&s_cnt, 1);
+__device__ __forceinline__ SplitOut split_point_anchor(const KArgs& a, double rd, double rm, double rr,
+                                                       double re, double guess, Anchor& A,
+                                                       bool sat_first = false) {
+  SplitOut o;
+  o.iters = 0;
+  o.bad = 0;
+  const double Cu = a.cvd * rd + a.cvv * rm + a.cl * rr;
+  const double Tu = a.Tref + (re - rm * a.Lp) * rcp64(Cu);
+  if (!isfinite(Tu) || !(Cu > 0.0)) {
+    o.T = __builtin_nan(""); o.rvs = rm; o.bad = 1;
+    return o;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    if (s_max) atomicMax(&a.stats[0], (unsigned)s_max);
-    if (s_nc) atomicAdd(&a.stats[1], (unsigned)s_nc);
-    if (s_bad) atomicOr(&a.stats[2], 1u);
-    if (s_cnt) atomicAdd((unsigned long long*)&a.stats[4], (unsigned long long)s_cnt);
+  // unsaturated test
+  bool unsat = false;
+  double rTu = 0.0;
+  if (!sat_first && Tu > 0.0) {
+    double dr;
+    rTu = (A.T0 > 0.0 && in_anchor(A, Tu)) ? rvs_near(a, A, Tu, &dr) : rho_vs(a, Tu);
+    unsat = rm <= rTu;
+  }
+  if (!unsat) {
+    // saturated branch: Newton from the warm start if it lies above the
+    // branch's lower bound max(Tu, 50 K)
+    double lo = Tu;
+    if (!(Tu > 50.0)) {
+      const double r = rho_vs(a, 50.0);
+      const double f = (Cu + (a.cvv - a.cl) * (r - rm)) * (50.0 - a.Tref) + r * a.Lp - re;
+      if (!(f < 0.0)) { o.T = __builtin_nan(""); o.rvs = rm; o.bad = 1; return o; }
+      lo = 50.0;
+    }
+    const double T0 = (guess > lo && guess < 600.0) ? guess : lo;
+    const NewtonOut n = newton_sat(a, Cu, rm, re, Tu, lo, T0, A);
+    o.iters = n.iters;
+    if (n.state == 2) { o.T = n.T; o.rvs = rho_vs(a, n.T); o.bad = 2; return o; }
+    if (n.state == 0 && (n.rvs <= rm || !(Tu > 0.0))) { o.T = n.T; o.rvs = n.rvs; return o; }
+    // the saturated root is not a solution: the air is unsaturated
+    if (!sat_first) { o.T = Tu; o.rvs = rm; return o; }   // ties at the branch point
+    rTu = rho_vs(a, Tu);
+  }
+  o.T = Tu;
+  o.rvs = rTu;
+  return o;
+}
+
+__device__ __forceinline__ SplitOut split_point(const KArgs& a, double rd, double rm, double rr,
+                                                double re, double guess) {
+  Anchor A;
+  A.T0 = 0.0; A.r0 = 0.0; A.inv0 = 0.0;
+  return split_point_anchor(a, rd, rm, rr, re, guess, A);
+}
+
+// Status words: only exceptional events touch global memory.  Iteration
+// maxima are merged per wave and written only when they exceed the stored
+// value; counts of non-converged or invalid states are rare.
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__device__ __forceinline__ void record_stats(const KArgs& a, int iters, int bad) {
+  const int m = wave_max(iters);
+  const int anybad = wave_max(bad);
+  const int lane = threadIdx.x & 63;
+  if (lane == 0) {
+    if (m > 0 && (unsigned)m > __builtin_nontemporal_load(&a.stats[0])) atomicMax(&a.stats[0], (unsigned)m);
+  }
+  if (anybad) {
+    if (bad == 2) atomicAdd(&a.stats[1], 1u);
+    if (bad == 1) atomicOr(&a.stats[2], 1u);
   }
 }
 
 // ---------------------------------------------------------------------------
 // pointwise state, fluxes, wave speed and sources
 // ---------------------------------------------------------------------------
+// reciprocal and fractional power in the bulk precision: hardware
+// reciprocal/log2/exp2 in FP32 (about 1 ulp), refined or library forms in FP64
+__device__ __forceinline__ float inv_b(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double inv_b(double x) { return rcp64(x); }
+__device__ __forceinline__ float pow_b(float x, float p) {
+  return __builtin_amdgcn_exp2f(p * __builtin_amdgcn_logf(x));
+}
+__device__ __forceinline__ double pow_b(double x, double p) { return pow(x, p); }
+
 template <typename R, int D, int RAIN>
 struct Pt {
   R m[D], u[D];
@@ -163,16 +272,17 @@ __device__ __forceinline__ void eval_point(const KArgs& a, const R* Uq, double T
   q.pp = (R)ppd;
   q.H = (R)(a.bg_E[iz] + a.bg_p[iz] + (double)Uq[V::E] + ppd);
   R uu = R(0);
+  const R irho = inv_b(q.rho);
   for (int i = 0; i < D; ++i) {
     q.m[i] = Uq[V::M0 + i];
-    q.u[i] = q.m[i] / q.rho;
+    q.u[i] = q.m[i] * irho;
     uu += q.u[i] * q.u[i];
   }
-  const R gam = R(1) + (R)gasR / (R)Cv;
-  q.cm = sqrt(gam * (R)p / q.rho);
+  const R gam = R(1) + (R)gasR * inv_b((R)Cv);
+  q.cm = sqrt(gam * (R)p * irho);
   if (RAIN) {
     if (a.vr_mode == 0) q.vr = (R)a.vr_const;
-    else q.vr = (R)a.vr_pref * (rr > 0.0 ? (R)pow(rr, 0.125) : R(0));
+    else q.vr = (R)a.vr_pref * (rr > 0.0 ? pow_b((R)rr, R(0.125)) : R(0));
     q.rrvr = q.rr * q.vr;
     q.rain_e = ((R)(a.cl * (T - a.Tref)) + R(0.5) * uu) * q.rrvr;
     q.rc = (R)rc;
@@ -230,9 +340,9 @@ __device__ __forceinline__ void sources(const KArgs& a, const R* Uq, const Pt<R,
     const R rrp = q.rr > R(0) ? q.rr : R(0);
     R p316 = R(0), p12 = R(0), p78 = R(0);
     if (rrp > R(0)) {
-      p316 = pow(rrp, R(0.1875));
+      p316 = pow_b(rrp, R(0.1875));
       p12 = sqrt(rrp);
-      p78 = pow(rrp, R(0.875));
+      p78 = pow_b(rrp, R(0.875));
     }
     const R Sev = (R(3.86e-3) - R(9.41e-5) * q.Tm) * (R(1) + R(9.1) * p316) * q.dvs * p12;
     const R au = q.rc - (R)a.q_au * q.rho;

@@ -33,18 +33,31 @@ __device__ __forceinline__ int elem_stride(const MemberDesc& md, int j) {
   return j == 0 ? 1 : (j == 1 ? md.n[0] : md.n[0] * md.n[1]);
 }
 
+// Work-item index of this block.  Consecutive blocks are dealt round-robin to
+// the 8 XCDs; the remap gives every XCD a contiguous range of items so that
+// neighbouring elements share an L2.
+__device__ __forceinline__ int item_of_block(int nitems) {
+  const int b = blockIdx.x;
+  const int per = (nitems + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+__host__ __device__ inline int grid_for_items(int nitems) { return ((nitems + 7) >> 3) << 3; }
+
 // ---------------------------------------------------------------------------
 // split kernel: (T, rho_vs) per node, or the API outputs (T, rho_v, rho_c)
 // ---------------------------------------------------------------------------
 template <typename R, int K, int D, int RAIN, int API>
 __global__ void __launch_bounds__(256)
-split_kernel(KArgs a, int item0, const R* __restrict__ U, const double* __restrict__ Tguess,
+split_kernel(KArgs a, int item0, int nitems, const R* __restrict__ U, const double* __restrict__ Tguess,
              double* __restrict__ oT, double* __restrict__ o1, double* __restrict__ o2) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
+  const int it_ = item_of_block(nitems);
+  if (it_ >= nitems) return;
   const int t = threadIdx.x;
-  const int2 item = a.items[item0 + blockIdx.x];
+  const int2 item = a.items[item0 + it_];
   const MemberDesc& md = a.mem[item.x];
   const int le = t / NP, n = t - le * NP;
   const int e = item.y + le;
@@ -80,53 +93,98 @@ split_kernel(KArgs a, int item0, const R* __restrict__ U, const double* __restri
       if (o1) o1[g] = rv;
       if (o2) o2[g] = rm - rv;
     } else {
-      o1[g] = s.rvs;
+      // the stored rho_vs(T) must be a fresh evaluation: it anchors later splits
+      o1[g] = (s.iters > 0 && s.bad == 0) ? rho_vs(a, s.T) : s.rvs;
     }
   }
-  record_stats<S::NT>(a, iters, bad, active);
+  record_stats(a, iters, bad);
 }
 
 // ---------------------------------------------------------------------------
 // right-hand side / stage kernel
 // ---------------------------------------------------------------------------
-// out = dU/dt                                  (MODE 0)
-// out = c0 U0 + c1 U + c2 dt_member dU/dt       (MODE 1, a Shu-Osher stage)
+// MODE 0: out = dU/dt
+// MODE 1: out = c0 U0 + c1 U + c2 dt_member dU/dt  (a Shu-Osher stage)
+// MODE 2: as MODE 1, then the split of the new state at every node, written
+//         to (oT, oS); Newton is warm-started and anchored at the input
+//         state's (T, rho_vs).  With `refresh` the stored rho_vs is a fresh
+//         evaluation at the new T (once per step), otherwise the anchored one.
+template <typename R, int D, int RAIN>
+struct Nb {
+  R U[Vars<D, RAIN>::NV];
+  double T, rvs;
+};
+
 template <typename R, int K, int D, int RAIN, int J>
-__device__ __forceinline__ void direction(const KArgs& a, const MemberDesc& md, const ElemCoord<D>& ec,
-                                          int e, int n, const int* idx, bool active, const R* Uq,
-                                          const Pt<R, D, RAIN>& q, R* Rv, R (*sF)[Shape<K, D>::NT],
-                                          const R* sD, const R* __restrict__ U,
+__device__ __forceinline__ void gather_nb(const MemberDesc& md, const ElemCoord<D>& ec, int e, int n,
+                                          int ij, const R* __restrict__ U,
                                           const double* __restrict__ auxT,
-                                          const double* __restrict__ auxS, long long N, int iz) {
+                                          const double* __restrict__ auxS, long long N,
+                                          Nb<R, D, RAIN>& nb, bool& wall, int& izn_off) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NV = V::NV;
   constexpr int STR = (J == 0) ? 1 : (J == 1 ? P1 : P1 * P1);
-  const int t = threadIdx.x;
-  R F[NV];
-  flux<R, D, RAIN, J>(q, F);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) sF[v][t] = F[v];
-  __syncthreads();
-  const int ij = idx[J];
-  if (active) {
-    const R s = (R)md.two_over_h[J];
-    const int base = t - ij * STR;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R acc = R(0);
-#pragma unroll
-      for (int b = 0; b < P1; ++b) acc += sD[ij * P1 + b] * sF[v][base + b * STR];
-      Rv[v] += s * acc;
-    }
-  }
-  __syncthreads();
-  if (!active || (ij != 0 && ij != K)) return;
-  // face with normal +e_J through this node: own side is K- when ij == K
   const bool plus = (ij == K);
   const int c = ec.c[J];
   const bool at_end = plus ? (c == md.n[J] - 1) : (c == 0);
-  const bool wall = at_end && md.bc[J] == 1;
+  wall = at_end && md.bc[J] == 1;
+  if (wall) return;
+  int cn = plus ? c + 1 : c - 1;
+  if (cn < 0) cn += md.n[J];
+  if (cn >= md.n[J]) cn -= md.n[J];
+  const int en = e + (cn - c) * elem_stride(md, J);
+  const int nn = plus ? n - K * STR : n + K * STR;
+  const long long gn = (md.eoff + en) * (long long)S::NP + nn;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) nb.U[v] = U[v * N + gn];
+  nb.T = auxT[gn];
+  nb.rvs = auxS[gn];
+  izn_off = (J == D - 1) ? (cn * P1 + (plus ? 0 : K)) : -1;
+}
+
+// Volume term (Section 3.2 weak form, Lobatto collocation): for direction J,
+// R += (2/h_J) sum_b Dhat[i_J][b] F_J(node b on this node's J-line).  The
+// fluxes of all directions are staged in LDS behind one barrier.
+template <typename R, int K, int D, int RAIN, int J>
+__device__ __forceinline__ void volume_dir(const MemberDesc& md, int ij, const R* sFJ, R* Rv,
+                                           const R* sD) {
+  using S = Shape<K, D>;
+  using V = Vars<D, RAIN>;
+  constexpr int P1 = S::P1, NV = V::NV, NT = S::NT;
+  constexpr int STR = (J == 0) ? 1 : (J == 1 ? P1 : P1 * P1);
+  const int t = threadIdx.x;
+  const R s = (R)md.two_over_h[J];
+  const int base = t - ij * STR;
+  R d[P1];
+#pragma unroll
+  for (int b = 0; b < P1; ++b) d[b] = sD[ij * P1 + b];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    R acc = R(0);
+#pragma unroll
+    for (int b = 0; b < P1; ++b) acc += d[b] * sFJ[v * NT + base + b * STR];
+    Rv[v] += s * acc;
+  }
+}
+
+template <typename R, int K, int D, int RAIN, int J>
+__device__ __forceinline__ void stage_flux(const Pt<R, D, RAIN>& q, R* sFJ) {
+  using V = Vars<D, RAIN>;
+  constexpr int NV = V::NV, NT = Shape<K, D>::NT;
+  R F[NV];
+  flux<R, D, RAIN, J>(q, F);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sFJ[v * NT + threadIdx.x] = F[v];
+}
+
+template <typename R, int K, int D, int RAIN, int J>
+__device__ __forceinline__ void face_dir(const KArgs& a, const MemberDesc& md, int ij, int iz,
+                                         const R* Uq, const Pt<R, D, RAIN>& q, const Nb<R, D, RAIN>& nb,
+                                         bool wall, int izn_off, R* Rv) {
+  using V = Vars<D, RAIN>;
+  constexpr int NV = V::NV;
+  const bool plus = (ij == K);
   R Un[NV];
   Pt<R, D, RAIN> qn;
   if (wall) {
@@ -136,41 +194,27 @@ __device__ __forceinline__ void direction(const KArgs& a, const MemberDesc& md, 
     qn = q;
     reflect<R, D, RAIN, J>(qn);
   } else {
-    int cn = plus ? c + 1 : c - 1;
-    if (cn < 0) cn += md.n[J];
-    if (cn >= md.n[J]) cn -= md.n[J];
-    const int en = e + (cn - c) * elem_stride(md, J);
-    const int nn = plus ? n - K * STR : n + K * STR;
-    const long long gn = (md.eoff + en) * (long long)S::NP + nn;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Un[v] = U[v * N + gn];
-    int izn = iz;
-    if (J == D - 1) izn = md.hoff + cn * P1 + (plus ? 0 : K);
-    eval_point<R, D, RAIN>(a, Un, auxT[gn], auxS[gn], izn, qn);
+    for (int v = 0; v < NV; ++v) Un[v] = nb.U[v];
+    const int izn = (J == D - 1) ? md.hoff + izn_off : iz;
+    eval_point<R, D, RAIN>(a, Un, nb.T, nb.rvs, izn, qn);
   }
-  R Fn[NV];
+  R F[NV], Fn[NV];
+  flux<R, D, RAIN, J>(q, F);
   flux<R, D, RAIN, J>(qn, Fn);
   const R lo = wave_speed<R, D, RAIN, J>(q);
   const R ln = wave_speed<R, D, RAIN, J>(qn);
   // Lambda = max over the two sides, ties to the minus side
-  R Lam;
-  if (plus) Lam = (lo >= ln) ? lo : ln;
-  else Lam = (ln >= lo) ? ln : lo;
+  const R Lam = plus ? ((lo >= ln) ? lo : ln) : ((ln >= lo) ? ln : lo);
   const R half = R(0.5);
   if (plus) {
     const R lift = (R)(md.two_over_h[J] / a.w[K]);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const R Fs = half * (F[v] + Fn[v]) + half * Lam * (Uq[v] - Un[v]);
-      Rv[v] -= lift * Fs;
-    }
+    for (int v = 0; v < NV; ++v) Rv[v] -= lift * (half * (F[v] + Fn[v]) + half * Lam * (Uq[v] - Un[v]));
   } else {
     const R lift = (R)(md.two_over_h[J] / a.w[0]);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      const R Fs = half * (Fn[v] + F[v]) + half * Lam * (Un[v] - Uq[v]);
-      Rv[v] += lift * Fs;
-    }
+    for (int v = 0; v < NV; ++v) Rv[v] += lift * (half * (Fn[v] + F[v]) + half * Lam * (Un[v] - Uq[v]));
   }
 }
 
@@ -178,15 +222,18 @@ template <typename R, int K, int D, int RAIN, int MODE>
 __global__ void __launch_bounds__(256)
 rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
            const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
-           const double* __restrict__ dt_m, double c0, double c1, double c2) {
+           const double* __restrict__ dt_m, double c0, double c1, double c2,
+           double* __restrict__ oT, double* __restrict__ oS, int refresh) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
-  __shared__ R sF[NV][S::NT];
+  __shared__ R sF[D][NV * S::NT];
   __shared__ R sD[P1 * P1];
+  const int it_ = item_of_block(a.nitems);
+  if (it_ >= a.nitems) return;
   const int t = threadIdx.x;
   if (t < P1 * P1) sD[t] = (R)a.Dhat[t];
-  const int2 item = a.items[blockIdx.x];
+  const int2 item = a.items[it_];
   const MemberDesc& md = a.mem[item.x];
   const int le = t / NP, n = t - le * NP;
   const int e = item.y + le;
@@ -200,8 +247,7 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   idx[2] = (D == 3) ? n / (P1 * P1) : 0;
   const int iz = md.hoff + ec.c[D - 1] * P1 + idx[D - 1];
   R Uq[NV];
-  Pt<R, D, RAIN> q;
-  double T = 0.0, rvs = 0.0;
+  double T = 300.0, rvs = 0.0;
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Uq[v] = U[v * N + g];
@@ -210,36 +256,85 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Uq[v] = R(0);
-    Uq[V::RD] = R(0);
-    T = 300.0;
-    rvs = 0.0;
   }
+  // neighbour traces: issue every gather before any arithmetic
+  Nb<R, D, RAIN> nb0, nb1, nb2;
+  bool w0 = false, w1 = false, w2 = false;
+  int z0 = -1, z1 = -1, z2 = -1;
+  const bool f0 = active && (idx[0] == 0 || idx[0] == K);
+  const bool f1 = active && (idx[1] == 0 || idx[1] == K);
+  const bool f2 = (D == 3) && active && (idx[2] == 0 || idx[2] == K);
+  if (f0) gather_nb<R, K, D, RAIN, 0>(md, ec, e, n, idx[0], U, auxT, auxS, N, nb0, w0, z0);
+  if (f1) gather_nb<R, K, D, RAIN, 1>(md, ec, e, n, idx[1], U, auxT, auxS, N, nb1, w1, z1);
+  if constexpr (D == 3) {
+    if (f2) gather_nb<R, K, D, RAIN, 2>(md, ec, e, n, idx[2], U, auxT, auxS, N, nb2, w2, z2);
+  }
+  Pt<R, D, RAIN> q;
   eval_point<R, D, RAIN>(a, Uq, T, rvs, active ? iz : md.hoff, q);
   R Rv[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) Rv[v] = R(0);
+  stage_flux<R, K, D, RAIN, 0>(q, sF[0]);
+  stage_flux<R, K, D, RAIN, 1>(q, sF[1]);
+  if constexpr (D == 3) stage_flux<R, K, D, RAIN, 2>(q, sF[2]);
   __syncthreads();
-  direction<R, K, D, RAIN, 0>(a, md, ec, e, n, idx, active, Uq, q, Rv, sF, sD, U, auxT, auxS, N, iz);
-  direction<R, K, D, RAIN, 1>(a, md, ec, e, n, idx, active, Uq, q, Rv, sF, sD, U, auxT, auxS, N, iz);
-  if constexpr (D == 3)
-    direction<R, K, D, RAIN, 2>(a, md, ec, e, n, idx, active, Uq, q, Rv, sF, sD, U, auxT, auxS, N, iz);
-  if (!active) return;
-  sources<R, D, RAIN>(a, Uq, q, Rv);
-  if (MODE == 0) {
+  if (active) {
+    volume_dir<R, K, D, RAIN, 0>(md, idx[0], sF[0], Rv, sD);
+    volume_dir<R, K, D, RAIN, 1>(md, idx[1], sF[1], Rv, sD);
+    if constexpr (D == 3) volume_dir<R, K, D, RAIN, 2>(md, idx[2], sF[2], Rv, sD);
+  }
+  if (f0) face_dir<R, K, D, RAIN, 0>(a, md, idx[0], iz, Uq, q, nb0, w0, z0, Rv);
+  if (f1) face_dir<R, K, D, RAIN, 1>(a, md, idx[1], iz, Uq, q, nb1, w1, z1, Rv);
+  if constexpr (D == 3) {
+    if (f2) face_dir<R, K, D, RAIN, 2>(a, md, idx[2], iz, Uq, q, nb2, w2, z2, Rv);
+  }
+  int iters = 0, bad = 0;
+  if (active) {
+    sources<R, D, RAIN>(a, Uq, q, Rv);
+    if (MODE == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) out[v * N + g] = Rv[v];
-  } else {
-    const R k2 = (R)(c2 * dt_m[item.x]);
-    const R k1 = (R)c1;
-    if (c0 != 0.0) {
-      const R k0 = (R)c0;
-#pragma unroll
-      for (int v = 0; v < NV; ++v) out[v * N + g] = k0 * U0[v * N + g] + k1 * Uq[v] + k2 * Rv[v];
+      for (int v = 0; v < NV; ++v) out[v * N + g] = Rv[v];
     } else {
+      const R k2 = (R)(c2 * dt_m[item.x]);
+      const R k1 = (R)c1;
+      R Un[NV];
+      if (c0 != 0.0) {
+        const R k0 = (R)c0;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) out[v * N + g] = k1 * Uq[v] + k2 * Rv[v];
+        for (int v = 0; v < NV; ++v) Un[v] = k0 * U0[v * N + g] + k1 * Uq[v] + k2 * Rv[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Un[v] = k1 * Uq[v] + k2 * Rv[v];
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) out[v * N + g] = Un[v];
+      if (MODE == 2) {
+        // split of the new state (FP64), warm-started at this node's (T, rho_vs)
+        const double rd = a.bg_rd[iz] + (double)Un[V::RD];
+        const double rm = a.bg_rm[iz] + (double)Un[V::RM];
+        const double rr = RAIN ? a.bg_rr[iz] + (double)Un[V::RR] : 0.0;
+        double ke = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          const double mi = (double)Un[V::M0 + i];
+          ke += mi * mi;
+        }
+        const double re = a.bg_E[iz] + (double)Un[V::E] - 0.5 * ke * rcp64(rd + rm + rr);
+        Anchor A;
+        A.T0 = 0.0; A.r0 = 0.0; A.inv0 = 0.0;
+        if (T > 150.0 && T < 600.0 && rvs > 0.0) {
+          A.T0 = T; A.r0 = rvs; A.inv0 = rcp64(T);
+        }
+        // the branch that held at this node before is tried first
+        const SplitOut s = split_point_anchor(a, rd, rm, rr, re, T, A, rvs < rm);
+        iters = s.iters;
+        bad = s.bad;
+        oT[g] = s.T;
+        oS[g] = (refresh && s.bad == 0) ? rho_vs(a, s.T) : s.rvs;
+      }
     }
   }
+  if (MODE == 2) record_stats(a, iters, bad);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,6 +343,7 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
 template <typename R, int K, int D, int RAIN>
 __global__ void __launch_bounds__(256)
 mass_kernel(KArgs a, int item0, const R* __restrict__ U, double* __restrict__ partial) {
+  // (blocks map to items in order here: partials are summed in a fixed order)
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NT = S::NT;

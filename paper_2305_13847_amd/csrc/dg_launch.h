@@ -43,29 +43,32 @@ struct Launch {
     if (nitems <= 0) return true;
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      dim3 grid(nitems), block(Shape<K_, D_>::NT);
+      dim3 grid(grid_for_items(nitems)), block(Shape<K_, D_>::NT);
       if (api)
-        hipLaunchKernelGGL((split_kernel<R, K_, D_, R_, 1>), grid, block, 0, s, a, item0,
+        hipLaunchKernelGGL((split_kernel<R, K_, D_, R_, 1>), grid, block, 0, s, a, item0, nitems,
                            (const R*)U, guess, oT, o1, o2);
       else
-        hipLaunchKernelGGL((split_kernel<R, K_, D_, R_, 0>), grid, block, 0, s, a, item0,
+        hipLaunchKernelGGL((split_kernel<R, K_, D_, R_, 0>), grid, block, 0, s, a, item0, nitems,
                            (const R*)U, guess, oT, o1, o2);
     });
   }
 
-  // mode 0: out = dU/dt; mode 1: out = c0 U0 + c1 U + c2 dt dU/dt
+  // mode 0: out = dU/dt; mode 1: out = c0 U0 + c1 U + c2 dt dU/dt; mode 2: mode 1 and the split
+  // of out into (oT, oS)
   static bool rhs(const KArgs& a, int K, int D, int rain, int mode, const void* U,
                   const double* auxT, const double* auxS, void* out, const void* U0,
-                  const double* dt, double c0, double c1, double c2, hipStream_t s) {
+                  const double* dt, double c0, double c1, double c2, double* oT, double* oS,
+                  int refresh, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      dim3 grid(a.nitems), block(Shape<K_, D_>::NT);
-      if (mode == 0)
-        hipLaunchKernelGGL((rhs_kernel<R, K_, D_, R_, 0>), grid, block, 0, s, a, (const R*)U, auxT,
-                           auxS, (R*)out, (const R*)U0, dt, c0, c1, c2);
-      else
-        hipLaunchKernelGGL((rhs_kernel<R, K_, D_, R_, 1>), grid, block, 0, s, a, (const R*)U, auxT,
-                           auxS, (R*)out, (const R*)U0, dt, c0, c1, c2);
+      dim3 grid(grid_for_items(a.nitems)), block(Shape<K_, D_>::NT);
+#define DGM_RHS(M)                                                                                \
+  hipLaunchKernelGGL((rhs_kernel<R, K_, D_, R_, M>), grid, block, 0, s, a, (const R*)U, auxT, auxS, \
+                     (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, refresh)
+      if (mode == 0) DGM_RHS(0);
+      else if (mode == 1) DGM_RHS(1);
+      else DGM_RHS(2);
+#undef DGM_RHS
     });
   }
 
@@ -83,7 +86,7 @@ struct Launch {
                       const double* auxS, const void* lam, void* out, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      hipLaunchKernelGGL((rhs_vjp_kernel<R, K_, D_, R_>), dim3(a.nitems), dim3(Shape<K_, D_>::NT), 0,
+      hipLaunchKernelGGL((rhs_vjp_kernel<R, K_, D_, R_>), dim3(grid_for_items(a.nitems)), dim3(Shape<K_, D_>::NT), 0,
                          s, a, (const R*)U, auxT, auxS, (const R*)lam, (R*)out);
     });
   }
@@ -93,7 +96,7 @@ struct Launch {
                         const double* rcb, void* out, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      hipLaunchKernelGGL((split_vjp_kernel<R, K_, D_, R_>), dim3(a.nitems),
+      hipLaunchKernelGGL((split_vjp_kernel<R, K_, D_, R_>), dim3(grid_for_items(a.nitems)),
                          dim3(Shape<K_, D_>::NT), 0, s, a, (const R*)U, auxT, auxS, Tb, rvb, rcb,
                          (R*)out);
     });

@@ -52,7 +52,9 @@ class dg_stats(ct.Structure):
 EXPORTS = ["dg_default_params", "dg_create", "dg_create_batch", "dg_set_background",
            "dg_member_offset", "dg_state_size", "dg_rhs", "dg_saturation_split", "dg_rk_step",
            "dg_rhs_vjp", "dg_saturation_split_vjp", "dg_rk_step_vjp", "dg_reduce_mass",
-           "dg_get_stats", "dg_reset_stats", "dg_destroy", "dg_last_error"]
+           "dg_get_stats", "dg_reset_stats", "dg_destroy", "dg_last_error", "dg_timing_enable",
+           "dg_timing_read"]
+DG_K_SPLIT, DG_K_STAGE, DG_K_ADJOINT, DG_K_OTHER = 0, 1, 2, 3
 
 _lib = None
 
@@ -85,6 +87,8 @@ def load(path: str = LIB_PATH):
     L.dg_get_stats.argtypes = [vp, ct.POINTER(dg_stats)]
     L.dg_reset_stats.argtypes = [vp]
     L.dg_destroy.argtypes = [vp]
+    L.dg_timing_enable.argtypes = [vp, ct.c_int]
+    L.dg_timing_read.argtypes = [vp, ct.c_int, dp, ct.POINTER(ct.c_longlong)]
     L.dg_last_error.argtypes = []
     L.dg_last_error.restype = ct.c_char_p
     for name in EXPORTS:
@@ -261,6 +265,14 @@ class DG:
         st = self.L.dg_get_stats(self.h, ct.byref(s))
         return dict(status=st, splits=s.splits, nonconverged=s.nonconverged, max_iters=s.max_iters,
                     nonfinite=s.nonfinite)
+
+    def timing(self, enable: bool = True):
+        _check(self.L.dg_timing_enable(self.h, int(bool(enable))))
+
+    def timing_read(self, kclass: int):
+        ms, n = ct.c_double(), ct.c_longlong()
+        _check(self.L.dg_timing_read(self.h, int(kclass), ct.byref(ms), ct.byref(n)))
+        return ms.value, n.value
 
     def reset_stats(self):
         _check(self.L.dg_reset_stats(self.h))

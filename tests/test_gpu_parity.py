@@ -176,3 +176,19 @@ def test_nonfinite_state_is_flagged():
     U[4, 3, 2] = 0.0
     dg.saturation_split(U)
     assert dg.stats()["status"] == 0
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-4)])
+def test_branch_switching_steps(prec, tol):
+    # about a third of the nodes saturated, strong flow: ~130 nodes change
+    # branch over these ten steps, so the warm-started splits must switch
+    c = synth.periodic_smooth(n=(16, 16), order=3, seed=7, sat_fraction=0.5)
+    dg, U = _gpu(c, prec)
+    dg.rk_step(U, 3 * c.dt, 10)
+    torch.cuda.synchronize()
+    st = dg.stats()
+    assert st["status"] == 0, st
+    ref, _ = O.Oracle.for_case(c).rk(c.U, 3 * c.dt, 10)
+    floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
+    err = rel_l2(c.mesh, U.double().cpu().numpy().reshape(c.U.shape), ref, floor=floor)
+    assert np.all(err < tol), err
