@@ -71,6 +71,10 @@ struct dg_handle {
   double* auxS = nullptr;
   double* auxT2 = nullptr;
   double* auxS2 = nullptr;
+  double* auxT3 = nullptr;        // adjoint: splits of the recomputed stages
+  double* auxS3 = nullptr;
+  double* auxT4 = nullptr;
+  double* auxS4 = nullptr;
   double* dt_d = nullptr;
   double* dt_h = nullptr;        // pinned staging for dt
   double* partial = nullptr;
@@ -178,6 +182,7 @@ static void free_all(dg_handle* h) {
   for (auto& b : h->stage) F(b);
   for (auto& b : h->stage_x) F(b);
   F(h->auxT); F(h->auxS); F(h->auxT2); F(h->auxS2);
+  F(h->auxT3); F(h->auxS3); F(h->auxT4); F(h->auxS4);
   F(h->dt_d); F(h->partial); F(h->red_out); F(h->stats);
   if (h->dt_h) (void)hipHostFree(h->dt_h);
 }
@@ -267,6 +272,11 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   ok = ok && A((void**)&h->auxS, sizeof(double) * h->nnodes);
   ok = ok && A((void**)&h->auxT2, sizeof(double) * h->nnodes);
   ok = ok && A((void**)&h->auxS2, sizeof(double) * h->nnodes);
+  ok = ok && A((void**)&h->auxT3, sizeof(double) * h->nnodes);
+  ok = ok && A((void**)&h->auxS3, sizeof(double) * h->nnodes);
+  ok = ok && A((void**)&h->auxT4, sizeof(double) * h->nnodes);
+  ok = ok && A((void**)&h->auxS4, sizeof(double) * h->nnodes);
+  for (auto& b : h->stage_x) ok = ok && A(&b, h->state_bytes);
   ok = ok && A((void**)&h->dt_d, sizeof(double) * nmembers);
   ok = ok && A((void**)&h->partial, sizeof(double) * 3 * h->items.size());
   ok = ok && A((void**)&h->red_out, sizeof(double) * 4);
@@ -546,21 +556,89 @@ extern "C" dg_status dg_reset_stats(dg_handle* h) {
   return DG_OK;
 }
 
+static bool do_vjp(dg_handle* h, const void* U, const double* aT, const double* aS, const void* lam,
+                   void* out, const void* X1, const void* X2, const double* dt, double cx1, double cx2,
+                   double c1, double c2, hipStream_t s) {
+  KTimer kt(h, DG_K_ADJOINT, s);
+  if (h->prec == DG_FP64)
+    return Launch<double>::rhs_vjp(h->ka, h->order, h->dim, h->rain, U, aT, aS, lam, out, X1, X2, dt, cx1,
+                                   cx2, c1, c2, s);
+  return Launch<float>::rhs_vjp(h->ka, h->order, h->dim, h->rain, U, aT, aS, lam, out, X1, X2, dt, cx1, cx2,
+                                c1, c2, s);
+}
+
 extern "C" dg_status dg_rhs_vjp(dg_handle* h, const void* U, const void* lam, void* Ub, hipStream_t s) {
-  (void)h; (void)U; (void)lam; (void)Ub; (void)s;
-  return fail(DG_EUNSUPPORTED, "dg_rhs_vjp not available in this build");
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !lam || !Ub) return fail(DG_EINVAL, "null pointer");
+  if (Ub == U || Ub == lam) return fail(DG_EINVAL, "U_bar must not alias U or dUdt_bar");
+  if (!do_split(h, U, nullptr, h->auxT, h->auxS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
+  do_vjp(h, U, h->auxT, h->auxS, lam, Ub, nullptr, nullptr, nullptr, 0, 0, 0.0, 1.0, s);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
 }
 
 extern "C" dg_status dg_saturation_split_vjp(dg_handle* h, const void* U, const double* Tb, const double* rvb,
                                              const double* rcb, void* Ub, hipStream_t s) {
-  (void)h; (void)U; (void)Tb; (void)rvb; (void)rcb; (void)Ub; (void)s;
-  return fail(DG_EUNSUPPORTED, "dg_saturation_split_vjp not available in this build");
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !Ub) return fail(DG_EINVAL, "null pointer");
+  if (Ub == U) return fail(DG_EINVAL, "U_bar must not alias U");
+  if (!do_split(h, U, nullptr, h->auxT, h->auxS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
+  KTimer kt(h, DG_K_ADJOINT, s);
+  bool ok;
+  if (h->prec == DG_FP64)
+    ok = Launch<double>::split_vjp(h->ka, h->order, h->dim, h->rain, U, h->auxT, h->auxS, Tb, rvb, rcb, Ub, s);
+  else
+    ok = Launch<float>::split_vjp(h->ka, h->order, h->dim, h->rain, U, h->auxT, h->auxS, Tb, rvb, rcb, Ub, s);
+  if (!ok) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
 }
 
-extern "C" dg_status dg_rk_step_vjp(dg_handle* h, const void* Un, const void* Ub1, void* Ub0, const double* dt,
+// Adjoint of one Shu-Osher step.  The stage states u1..u3 (and their splits)
+// are recomputed from U_n with the forward stage kernels, then the stages are
+// transposed in reverse order:
+//   SSPRK(4,3): r3 = w + dt/2 J3^T w;  r2 = r3/3 + dt/6 J2^T r3;
+//               r1 = r2 + dt/2 J1^T r2; r0 = 2/3 r3 + r1 + dt/2 J0^T r1
+//   SSPRK(3,3): r2 = 2/3 w + 2 dt/3 J2^T w; r1 = r2/4 + dt/4 J1^T r2;
+//               r0 = w/3 + 3/4 r2 + r1 + dt J0^T r1
+// with J_s the Jacobian of the right-hand side at stage state u_s.
+extern "C" dg_status dg_rk_step_vjp(dg_handle* h, const void* Un, const void* W, void* Ub0, const double* dt,
                                     hipStream_t s) {
-  (void)h; (void)Un; (void)Ub1; (void)Ub0; (void)dt; (void)s;
-  return fail(DG_EUNSUPPORTED, "dg_rk_step_vjp not available in this build");
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!Un || !W || !Ub0 || !dt) return fail(DG_EINVAL, "null pointer");
+  if (Ub0 == Un || Ub0 == W) return fail(DG_EINVAL, "U_n_bar must not alias U_n or U_np1_bar");
+  st = upload_dt(h, dt, s);
+  if (st != DG_OK) return st;
+  void* u1 = h->stage_x[0];
+  void* u2 = h->stage_x[1];
+  void* u3 = h->stage_x[2];
+  void* B1 = h->stage[0];
+  void* B2 = h->stage[1];
+  void* B3 = h->stage_x[3];
+  double* aT[4] = {h->auxT, h->auxT2, h->auxT3, h->auxT4};
+  double* aS[4] = {h->auxS, h->auxS2, h->auxS3, h->auxS4};
+  // recompute the stages
+  do_split(h, Un, nullptr, aT[0], aS[0], nullptr, 0, s);
+  if (h->rk == DG_SSPRK43) {
+    do_rhs(h, 2, Un, aT[0], aS[0], u1, Un, kSSP43[0].c0, kSSP43[0].c1, kSSP43[0].c2, s, aT[1], aS[1], 0);
+    do_rhs(h, 2, u1, aT[1], aS[1], u2, Un, kSSP43[1].c0, kSSP43[1].c1, kSSP43[1].c2, s, aT[2], aS[2], 0);
+    do_rhs(h, 2, u2, aT[2], aS[2], u3, Un, kSSP43[2].c0, kSSP43[2].c1, kSSP43[2].c2, s, aT[3], aS[3], 0);
+    do_vjp(h, u3, aT[3], aS[3], W, B3, nullptr, nullptr, h->dt_d, 0, 0, 1.0, 0.5, s);
+    do_vjp(h, u2, aT[2], aS[2], B3, B2, nullptr, nullptr, h->dt_d, 0, 0, 1.0 / 3.0, 1.0 / 6.0, s);
+    do_vjp(h, u1, aT[1], aS[1], B2, B1, nullptr, nullptr, h->dt_d, 0, 0, 1.0, 0.5, s);
+    do_vjp(h, Un, aT[0], aS[0], B1, Ub0, B3, nullptr, h->dt_d, 2.0 / 3.0, 0, 1.0, 0.5, s);
+  } else {
+    do_rhs(h, 2, Un, aT[0], aS[0], u1, Un, kSSP33[0].c0, kSSP33[0].c1, kSSP33[0].c2, s, aT[1], aS[1], 0);
+    do_rhs(h, 2, u1, aT[1], aS[1], u2, Un, kSSP33[1].c0, kSSP33[1].c1, kSSP33[1].c2, s, aT[2], aS[2], 0);
+    do_vjp(h, u2, aT[2], aS[2], W, B2, nullptr, nullptr, h->dt_d, 0, 0, 2.0 / 3.0, 2.0 / 3.0, s);
+    do_vjp(h, u1, aT[1], aS[1], B2, B1, nullptr, nullptr, h->dt_d, 0, 0, 0.25, 0.25, s);
+    do_vjp(h, Un, aT[0], aS[0], B1, Ub0, W, B2, h->dt_d, 1.0 / 3.0, 0.75, 1.0, 1.0, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
 }
 
 extern "C" dg_status dg_timing_enable(dg_handle* h, int enable) {

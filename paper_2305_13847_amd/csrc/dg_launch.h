@@ -81,13 +81,16 @@ struct Launch {
     });
   }
 
-  // adjoint of the right-hand side (dg_vjp.h)
+  // adjoint of the right-hand side (dg_vjp.h):
+  // out = cx1 X1 + cx2 X2 + c1 lam + c2 dt (d rhs/dU)^T lam   (dt = 1 if null)
   static bool rhs_vjp(const KArgs& a, int K, int D, int rain, const void* U, const double* auxT,
-                      const double* auxS, const void* lam, void* out, hipStream_t s) {
+                      const double* auxS, const void* lam, void* out, const void* X1, const void* X2,
+                      const double* dt, double cx1, double cx2, double c1, double c2, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      hipLaunchKernelGGL((rhs_vjp_kernel<R, K_, D_, R_>), dim3(grid_for_items(a.nitems)), dim3(Shape<K_, D_>::NT), 0,
-                         s, a, (const R*)U, auxT, auxS, (const R*)lam, (R*)out);
+      hipLaunchKernelGGL((rhs_vjp_kernel<R, K_, D_, R_>), dim3(grid_for_items(a.nitems)),
+                         dim3(Shape<K_, D_>::NT), 0, s, a, (const R*)U, auxT, auxS, (const R*)lam,
+                         (R*)out, (const R*)X1, (const R*)X2, dt, cx1, cx2, c1, c2);
     });
   }
 
