@@ -177,6 +177,24 @@ dg_status dg_reset_stats(dg_handle* h);
 
 dg_status dg_destroy(dg_handle* h);
 
+/* Launch geometry: elements per block (1 .. 256 / (k+1)^dim) and persistent
+ * blocks per compute unit (0: one block per work item; n > 0: a grid of
+ * n x CUs blocks that walk the work items).  Not a hot call: synchronises. */
+dg_status dg_set_launch(dg_handle* h, int elems_per_block, int persist_per_cu);
+dg_status dg_get_launch(const dg_handle* h, int* elems_per_block, int* persist_per_cu);
+
+/* Autotuner: times nsteps RK steps of a copy of U (device) for every
+ * candidate geometry (elements per block {max, max/2, max/4} x persistent
+ * blocks per CU {0, 1, 2, 4}), keeps the fastest and reports it (any output
+ * pointer may be NULL; best_ms is per step).  U is not modified. */
+dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, int nsteps, int* best_epb,
+                      int* best_persist, double* best_ms);
+
+/* dg_rk_step replayed from a captured hipGraph: the first call for a given
+ * (U, nsteps, geometry) captures every kernel of the nsteps steps, later
+ * calls replay it.  Kernel timing must be disabled. */
+dg_status dg_rk_step_graph(dg_handle* h, void* U, const double* dt, int nsteps, hipStream_t stream);
+
 /* Kernel timing (instrumentation).  While enabled, every kernel the library
  * launches is bracketed by HIP events on its stream; dg_timing_read
  * synchronises and returns the accumulated device time and launch count of a

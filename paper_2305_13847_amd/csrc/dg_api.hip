@@ -82,6 +82,17 @@ struct dg_handle {
   unsigned* stats = nullptr;
   long long splits = 0;          // node splits enqueued since the last reset
   KArgs ka{};
+  // launch geometry
+  int epb = 1;                   // elements per block
+  int persist = 0;               // persistent blocks per CU (0: one block per item)
+  int ncu = 256;
+  long long items_cap = 0;       // device capacity of the item table
+  // captured multi-step graph
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  const void* graph_U = nullptr;
+  int graph_nsteps = -1, graph_epb = -1, graph_persist = -1;
   // kernel timing
   bool timing = false;
   std::vector<hipEvent_t> ev;        // pairs (start, stop)
@@ -185,6 +196,9 @@ static void free_all(dg_handle* h) {
   F(h->auxT3); F(h->auxS3); F(h->auxT4); F(h->auxS4);
   F(h->dt_d); F(h->partial); F(h->red_out); F(h->stats);
   if (h->dt_h) (void)hipHostFree(h->dt_h);
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
 }
 
 static dg_status validate_mesh(const dg_mesh* m, int dim) {
@@ -196,6 +210,30 @@ static dg_status validate_mesh(const dg_mesh* m, int dim) {
       return fail(DG_EINVAL, "mesh.bc[%d] must be DG_PERIODIC or DG_SLIPWALL", a);
   }
   return DG_OK;
+}
+
+// (Re)build the work-item table for `epb` elements per block.
+static void build_items(dg_handle* h, int epb) {
+  h->items.clear();
+  h->item_off.clear();
+  for (int m = 0; m < h->nmembers; ++m) {
+    h->item_off.push_back((int)h->items.size());
+    for (int e0 = 0; e0 < h->mem[m].ne; e0 += epb) h->items.push_back(make_int2(m, e0));
+  }
+  h->item_off.push_back((int)h->items.size());
+  h->epb = epb;
+}
+
+static LaunchCfg launch_cfg(const dg_handle* h) {
+  LaunchCfg lc;
+  lc.threads = h->epb * h->np;
+  const int n = (int)h->items.size();
+  lc.grid = grid_for_items(n);
+  if (h->persist > 0) {
+    const int pg = ((h->persist * h->ncu + 7) / 8) * 8;
+    if (pg < lc.grid) lc.grid = pg;
+  }
+  return lc;
 }
 
 extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int order, int nvars,
@@ -225,6 +263,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   const int epb = elems_per_block(order, dim);
   long long eoff = 0;
   int hoff = 0;
+  long long items_max = 0;
   for (int m = 0; m < nmembers; ++m) {
     const dg_mesh& g = meshes[m];
     MemberDesc md{};
@@ -246,15 +285,21 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
     md.ne = (int)ne;
     md.eoff = eoff;
     md.hoff = hoff;
-    h->item_off.push_back((int)h->items.size());
-    for (int e0 = 0; e0 < md.ne; e0 += epb) h->items.push_back(make_int2(m, e0));
+    items_max += ne;
     h->hoff.push_back(hoff);
     eoff += ne;
     hoff += md.n[dim - 1] * p1;
     h->mem.push_back(md);
   }
-  h->item_off.push_back((int)h->items.size());
   h->hoff.push_back(hoff);
+  build_items(h, epb);
+  h->items_cap = items_max;
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      h->ncu = prop.multiProcessorCount;
+  }
   h->bg_set.assign(nmembers, 0);
   h->etot = eoff;
   h->nnodes = eoff * h->np;
@@ -265,7 +310,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   auto A = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, bytes) == hipSuccess; };
   bool ok = true;
   ok = ok && A((void**)&h->mem_d, sizeof(MemberDesc) * nmembers);
-  ok = ok && A((void**)&h->items_d, sizeof(int2) * h->items.size());
+  ok = ok && A((void**)&h->items_d, sizeof(int2) * h->items_cap);
   for (auto& b : h->bg_d) ok = ok && A((void**)&b, sizeof(double) * hoff);
   for (auto& b : h->stage) ok = ok && A(&b, h->state_bytes);
   ok = ok && A((void**)&h->auxT, sizeof(double) * h->nnodes);
@@ -278,7 +323,8 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   ok = ok && A((void**)&h->auxS4, sizeof(double) * h->nnodes);
   for (auto& b : h->stage_x) ok = ok && A(&b, h->state_bytes);
   ok = ok && A((void**)&h->dt_d, sizeof(double) * nmembers);
-  ok = ok && A((void**)&h->partial, sizeof(double) * 3 * h->items.size());
+  ok = ok && A((void**)&h->partial, sizeof(double) * 3 * h->items_cap);
+  ok = ok && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) == hipSuccess;
   ok = ok && A((void**)&h->red_out, sizeof(double) * 4);
   ok = ok && A((void**)&h->stats, sizeof(unsigned) * 8);
   ok = ok && hipHostMalloc((void**)&h->dt_h, sizeof(double) * nmembers) == hipSuccess;
@@ -399,9 +445,10 @@ static bool do_split(dg_handle* h, const void* U, const double* guess, double* o
   const int n = (int)h->items.size();
   KTimer kt(h, DG_K_SPLIT, s);
   h->splits += h->nnodes;
+  const LaunchCfg lc = launch_cfg(h);
   if (h->prec == DG_FP64)
-    return Launch<double>::split(h->ka, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
-  return Launch<float>::split(h->ka, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
+    return Launch<double>::split(h->ka, lc, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
+  return Launch<float>::split(h->ka, lc, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
 }
 
 static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, const double* aS, void* out,
@@ -409,11 +456,12 @@ static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, cons
                    double* oT = nullptr, double* oS = nullptr, int refresh = 0) {
   KTimer kt(h, DG_K_STAGE, s);
   if (mode == 2) h->splits += h->nnodes;
+  const LaunchCfg lc = launch_cfg(h);
   if (h->prec == DG_FP64)
-    return Launch<double>::rhs(h->ka, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1,
-                               c2, oT, oS, refresh, s);
-  return Launch<float>::rhs(h->ka, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1, c2,
-                            oT, oS, refresh, s);
+    return Launch<double>::rhs(h->ka, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0,
+                               c1, c2, oT, oS, refresh, s);
+  return Launch<float>::rhs(h->ka, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1,
+                            c2, oT, oS, refresh, s);
 }
 
 extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t s) {
@@ -523,10 +571,11 @@ extern "C" dg_status dg_reduce_mass(dg_handle* h, int member, const void* U, dou
   const int i0 = member < 0 ? 0 : h->item_off[member];
   const int i1 = member < 0 ? (int)h->items.size() : h->item_off[member + 1];
   const int n = i1 - i0;
+  const LaunchCfg lc = launch_cfg(h);
   if (h->prec == DG_FP64)
-    Launch<double>::mass(h->ka, h->order, h->dim, h->rain, i0, n, U, h->partial, s);
+    Launch<double>::mass(h->ka, lc, h->order, h->dim, h->rain, i0, n, U, h->partial, s);
   else
-    Launch<float>::mass(h->ka, h->order, h->dim, h->rain, i0, n, U, h->partial, s);
+    Launch<float>::mass(h->ka, lc, h->order, h->dim, h->rain, i0, n, U, h->partial, s);
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(256), 0, s, h->partial, n, h->red_out);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(out3, h->red_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -560,11 +609,12 @@ static bool do_vjp(dg_handle* h, const void* U, const double* aT, const double* 
                    void* out, const void* X1, const void* X2, const double* dt, double cx1, double cx2,
                    double c1, double c2, hipStream_t s) {
   KTimer kt(h, DG_K_ADJOINT, s);
+  const LaunchCfg lc = launch_cfg(h);
   if (h->prec == DG_FP64)
-    return Launch<double>::rhs_vjp(h->ka, h->order, h->dim, h->rain, U, aT, aS, lam, out, X1, X2, dt, cx1,
+    return Launch<double>::rhs_vjp(h->ka, lc, h->order, h->dim, h->rain, U, aT, aS, lam, out, X1, X2, dt, cx1,
                                    cx2, c1, c2, s);
-  return Launch<float>::rhs_vjp(h->ka, h->order, h->dim, h->rain, U, aT, aS, lam, out, X1, X2, dt, cx1, cx2,
-                                c1, c2, s);
+  return Launch<float>::rhs_vjp(h->ka, lc, h->order, h->dim, h->rain, U, aT, aS, lam, out, X1, X2, dt, cx1,
+                                cx2, c1, c2, s);
 }
 
 extern "C" dg_status dg_rhs_vjp(dg_handle* h, const void* U, const void* lam, void* Ub, hipStream_t s) {
@@ -587,10 +637,11 @@ extern "C" dg_status dg_saturation_split_vjp(dg_handle* h, const void* U, const 
   if (!do_split(h, U, nullptr, h->auxT, h->auxS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
   KTimer kt(h, DG_K_ADJOINT, s);
   bool ok;
+  const LaunchCfg lc = launch_cfg(h);
   if (h->prec == DG_FP64)
-    ok = Launch<double>::split_vjp(h->ka, h->order, h->dim, h->rain, U, h->auxT, h->auxS, Tb, rvb, rcb, Ub, s);
+    ok = Launch<double>::split_vjp(h->ka, lc, h->order, h->dim, h->rain, U, h->auxT, h->auxS, Tb, rvb, rcb, Ub, s);
   else
-    ok = Launch<float>::split_vjp(h->ka, h->order, h->dim, h->rain, U, h->auxT, h->auxS, Tb, rvb, rcb, Ub, s);
+    ok = Launch<float>::split_vjp(h->ka, lc, h->order, h->dim, h->rain, U, h->auxT, h->auxS, Tb, rvb, rcb, Ub, s);
   if (!ok) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
   HIP_TRY(hipGetLastError());
   return DG_OK;
@@ -664,5 +715,120 @@ extern "C" dg_status dg_timing_read(dg_handle* h, int kclass, double* total_ms, 
   timing_flush(h);
   if (total_ms) *total_ms = h->t_ms[kclass];
   if (launches) *launches = h->t_n[kclass];
+  return DG_OK;
+}
+
+static dg_status upload_items(dg_handle* h) {
+  HIP_TRY(hipMemcpy(h->items_d, h->items.data(), sizeof(int2) * h->items.size(), hipMemcpyHostToDevice));
+  h->ka.nitems = (int)h->items.size();
+  return DG_OK;
+}
+
+extern "C" dg_status dg_set_launch(dg_handle* h, int epb, int persist) {
+  if (!h) return fail(DG_EINVAL, "null handle");
+  const int emax = elems_per_block(h->order, h->dim);
+  if (epb < 1 || epb > emax) return fail(DG_EINVAL, "elements per block must be in 1..%d", emax);
+  if (persist < 0 || persist > 64) return fail(DG_EINVAL, "persistent blocks per CU must be in 0..64");
+  HIP_TRY(hipDeviceSynchronize());
+  if (epb != h->epb) {
+    build_items(h, epb);
+    dg_status st = upload_items(h);
+    if (st != DG_OK) return st;
+  }
+  h->persist = persist;
+  return DG_OK;
+}
+
+extern "C" dg_status dg_get_launch(const dg_handle* h, int* epb, int* persist) {
+  if (!h) return fail(DG_EINVAL, "null handle");
+  if (epb) *epb = h->epb;
+  if (persist) *persist = h->persist;
+  return DG_OK;
+}
+
+// Time `nsteps` RK steps of a copy of U for each launch geometry and keep the
+// fastest: elements per block in {max, max/2, max/4} x persistent blocks per
+// CU in {0, 1, 2, 4}.
+extern "C" dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, int nsteps, int* best_epb,
+                                 int* best_persist, double* best_ms) {
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !dt || nsteps < 1) return fail(DG_EINVAL, "bad autotune arguments");
+  st = upload_dt(h, dt, 0);
+  if (st != DG_OK) return st;
+  const int emax = elems_per_block(h->order, h->dim);
+  const int cand_e[3] = {emax, emax / 2, emax / 4};
+  const int cand_p[4] = {0, 1, 2, 4};
+  void* W = h->stage_x[0];
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const bool timing = h->timing;
+  h->timing = false;
+  double best = 1e300;
+  int be = h->epb, bp = h->persist;
+  for (int ie = 0; ie < 3; ++ie) {
+    if (cand_e[ie] < 1 || (ie > 0 && cand_e[ie] == cand_e[ie - 1])) continue;
+    for (int ip = 0; ip < 4; ++ip) {
+      st = dg_set_launch(h, cand_e[ie], cand_p[ip]);
+      if (st != DG_OK) { h->timing = timing; return st; }
+      HIP_TRY(hipMemcpy(W, U, h->state_bytes, hipMemcpyDeviceToDevice));
+      int cur = 0;
+      rk_one(h, W, true, &cur, 0);                       // warm-up
+      HIP_TRY(hipMemcpy(W, U, h->state_bytes, hipMemcpyDeviceToDevice));
+      HIP_TRY(hipEventRecord(e0, 0));
+      for (int i = 0; i < nsteps; ++i) rk_one(h, W, i == 0, &cur, 0);
+      HIP_TRY(hipEventRecord(e1, 0));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; be = cand_e[ie]; bp = cand_p[ip]; }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->timing = timing;
+  st = dg_set_launch(h, be, bp);
+  if (st != DG_OK) return st;
+  if (best_epb) *best_epb = be;
+  if (best_persist) *best_persist = bp;
+  if (best_ms) *best_ms = best / nsteps;
+  return DG_OK;
+}
+
+// nsteps RK steps replayed from a captured hipGraph.  The graph holds the
+// split and stage kernels of all steps; dt is read from device memory, which
+// is updated before each replay.  It is captured again when U, nsteps or the
+// launch geometry change.
+extern "C" dg_status dg_rk_step_graph(dg_handle* h, void* U, const double* dt, int nsteps, hipStream_t s) {
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !dt) return fail(DG_EINVAL, "null pointer");
+  if (nsteps < 1) return fail(DG_EINVAL, "nsteps must be >= 1");
+  if (h->timing) return fail(DG_EINVAL, "disable kernel timing before using graphs");
+  if (!h->graph_exec || h->graph_U != U || h->graph_nsteps != nsteps || h->graph_epb != h->epb ||
+      h->graph_persist != h->persist) {
+    if (h->graph_exec) { (void)hipGraphExecDestroy(h->graph_exec); h->graph_exec = nullptr; }
+    if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+    HIP_TRY(hipStreamSynchronize(s));
+    HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+    int cur = 0;
+    dg_status cs = DG_OK;
+    for (int i = 0; i < nsteps && cs == DG_OK; ++i) cs = rk_one(h, U, i == 0, &cur, h->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
+    if (cs != DG_OK) { if (g) (void)hipGraphDestroy(g); return cs; }
+    if (ce != hipSuccess) return fail(DG_EHIP, "graph capture failed: %s", hipGetErrorString(ce));
+    h->graph = g;
+    HIP_TRY(hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+    h->graph_U = U;
+    h->graph_nsteps = nsteps;
+    h->graph_epb = h->epb;
+    h->graph_persist = h->persist;
+  }
+  st = upload_dt(h, dt, s);
+  if (st != DG_OK) return st;
+  HIP_TRY(hipGraphLaunch(h->graph_exec, s));
+  h->splits += (long long)h->nnodes * nsteps * (h->rk == DG_SSPRK43 ? 4 : 3);
   return DG_OK;
 }

@@ -33,14 +33,28 @@ __device__ __forceinline__ int elem_stride(const MemberDesc& md, int j) {
   return j == 0 ? 1 : (j == 1 ? md.n[0] : md.n[0] * md.n[1]);
 }
 
-// Work-item index of this block.  Consecutive blocks are dealt round-robin to
-// the 8 XCDs; the remap gives every XCD a contiguous range of items so that
-// neighbouring elements share an L2.
-__device__ __forceinline__ int item_of_block(int nitems) {
-  const int b = blockIdx.x;
-  const int per = (nitems + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
-}
+// Work items (member, first element) of EPB elements are dealt to blocks.
+// Consecutive blocks go round-robin to the 8 XCDs; XCD x owns the contiguous
+// item range [x per, (x+1) per), so neighbouring elements share an L2.  With a
+// persistent grid (fewer blocks than items) each block walks its XCD's range
+// with stride gridDim/8.  gridDim.x is always a multiple of 8.
+struct ItemWalk {
+  int per, g8, x, l, nitems;
+  __device__ __forceinline__ explicit ItemWalk(int n) {
+    nitems = n;
+    per = (n + 7) >> 3;
+    g8 = gridDim.x >> 3;
+    x = blockIdx.x & 7;
+    l = blockIdx.x >> 3;
+  }
+  // item of the k-th iteration, or -1 when the walk is over (uniform per block)
+  __device__ __forceinline__ int item(int k) const {
+    const int li = l + k * g8;
+    if (li >= per) return -1;
+    const int it = x * per + li;
+    return it < nitems ? it : -1;
+  }
+};
 
 __host__ __device__ inline int grid_for_items(int nitems) { return ((nitems + 7) >> 3) << 3; }
 
@@ -54,8 +68,10 @@ split_kernel(KArgs a, int item0, int nitems, const R* __restrict__ U, const doub
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
-  const int it_ = item_of_block(nitems);
-  if (it_ >= nitems) return;
+  const ItemWalk walk(nitems);
+  for (int k = 0;; ++k) {
+  const int it_ = walk.item(k);
+  if (it_ < 0) break;
   const int t = threadIdx.x;
   const int2 item = a.items[item0 + it_];
   const MemberDesc& md = a.mem[item.x];
@@ -98,6 +114,7 @@ split_kernel(KArgs a, int item0, int nitems, const R* __restrict__ U, const doub
     }
   }
   record_stats(a, iters, bad);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -151,9 +168,10 @@ __device__ __forceinline__ void volume_dir(const MemberDesc& md, int ij, const R
                                            const R* sD) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
-  constexpr int P1 = S::P1, NV = V::NV, NT = S::NT;
+  constexpr int P1 = S::P1, NV = V::NV;
   constexpr int STR = (J == 0) ? 1 : (J == 1 ? P1 : P1 * P1);
   const int t = threadIdx.x;
+  const int NT = blockDim.x;
   const R s = (R)md.two_over_h[J];
   const int base = t - ij * STR;
   R d[P1];
@@ -171,7 +189,8 @@ __device__ __forceinline__ void volume_dir(const MemberDesc& md, int ij, const R
 template <typename R, int K, int D, int RAIN, int J>
 __device__ __forceinline__ void stage_flux(const Pt<R, D, RAIN>& q, R* sFJ) {
   using V = Vars<D, RAIN>;
-  constexpr int NV = V::NV, NT = Shape<K, D>::NT;
+  constexpr int NV = V::NV;
+  const int NT = blockDim.x;
   R F[NV];
   flux<R, D, RAIN, J>(q, F);
 #pragma unroll
@@ -229,10 +248,12 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
   __shared__ R sF[D][NV * S::NT];
   __shared__ R sD[P1 * P1];
-  const int it_ = item_of_block(a.nitems);
-  if (it_ >= a.nitems) return;
   const int t = threadIdx.x;
   if (t < P1 * P1) sD[t] = (R)a.Dhat[t];
+  const ItemWalk walk(a.nitems);
+  for (int kk = 0;; ++kk) {
+  const int it_ = walk.item(kk);
+  if (it_ < 0) break;
   const int2 item = a.items[it_];
   const MemberDesc& md = a.mem[item.x];
   const int le = t / NP, n = t - le * NP;
@@ -335,6 +356,8 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
     }
   }
   if (MODE == 2) record_stats(a, iters, bad);
+  __syncthreads();   // sF is reused by the next item
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -346,8 +369,9 @@ mass_kernel(KArgs a, int item0, const R* __restrict__ U, double* __restrict__ pa
   // (blocks map to items in order here: partials are summed in a fixed order)
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
-  constexpr int P1 = S::P1, NP = S::NP, NT = S::NT;
-  __shared__ double sm[3][NT];
+  constexpr int P1 = S::P1, NP = S::NP;
+  __shared__ double sm[3][S::NT];
+  const int NT = blockDim.x;
   const int t = threadIdx.x;
   const int2 item = a.items[item0 + blockIdx.x];
   const MemberDesc& md = a.mem[item.x];

@@ -34,16 +34,22 @@ inline int elems_per_block(int K, int D) {
   return 256 / np > 0 ? 256 / np : 1;
 }
 
+// Launch geometry of a handle: threads per block (EPB elements) and grid size.
+struct LaunchCfg {
+  int threads;
+  int grid;
+};
+
 template <typename R>
 struct Launch {
   // API != 0: write T, rho_v, rho_c; otherwise T and rho_vs(T)
-  static bool split(const KArgs& a, int K, int D, int rain, int item0, int nitems, const void* U,
-                    const double* guess, double* oT, double* o1, double* o2, int api,
+  static bool split(const KArgs& a, LaunchCfg lc, int K, int D, int rain, int item0, int nitems,
+                    const void* U, const double* guess, double* oT, double* o1, double* o2, int api,
                     hipStream_t s) {
     if (nitems <= 0) return true;
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      dim3 grid(grid_for_items(nitems)), block(Shape<K_, D_>::NT);
+      dim3 grid(lc.grid), block(lc.threads);
       if (api)
         hipLaunchKernelGGL((split_kernel<R, K_, D_, R_, 1>), grid, block, 0, s, a, item0, nitems,
                            (const R*)U, guess, oT, o1, o2);
@@ -55,13 +61,13 @@ struct Launch {
 
   // mode 0: out = dU/dt; mode 1: out = c0 U0 + c1 U + c2 dt dU/dt; mode 2: mode 1 and the split
   // of out into (oT, oS)
-  static bool rhs(const KArgs& a, int K, int D, int rain, int mode, const void* U,
+  static bool rhs(const KArgs& a, LaunchCfg lc, int K, int D, int rain, int mode, const void* U,
                   const double* auxT, const double* auxS, void* out, const void* U0,
                   const double* dt, double c0, double c1, double c2, double* oT, double* oS,
                   int refresh, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      dim3 grid(grid_for_items(a.nitems)), block(Shape<K_, D_>::NT);
+      dim3 grid(lc.grid), block(lc.threads);
 #define DGM_RHS(M)                                                                                \
   hipLaunchKernelGGL((rhs_kernel<R, K_, D_, R_, M>), grid, block, 0, s, a, (const R*)U, auxT, auxS, \
                      (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, refresh)
@@ -72,35 +78,34 @@ struct Launch {
     });
   }
 
-  static bool mass(const KArgs& a, int K, int D, int rain, int item0, int nitems, const void* U,
-                   double* partial, hipStream_t s) {
+  static bool mass(const KArgs& a, LaunchCfg lc, int K, int D, int rain, int item0, int nitems,
+                   const void* U, double* partial, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      hipLaunchKernelGGL((mass_kernel<R, K_, D_, R_>), dim3(nitems), dim3(Shape<K_, D_>::NT), 0, s,
-                         a, item0, (const R*)U, partial);
+      hipLaunchKernelGGL((mass_kernel<R, K_, D_, R_>), dim3(nitems), dim3(lc.threads), 0, s, a, item0,
+                         (const R*)U, partial);
     });
   }
 
   // adjoint of the right-hand side (dg_vjp.h):
   // out = cx1 X1 + cx2 X2 + c1 lam + c2 dt (d rhs/dU)^T lam   (dt = 1 if null)
-  static bool rhs_vjp(const KArgs& a, int K, int D, int rain, const void* U, const double* auxT,
-                      const double* auxS, const void* lam, void* out, const void* X1, const void* X2,
-                      const double* dt, double cx1, double cx2, double c1, double c2, hipStream_t s) {
+  static bool rhs_vjp(const KArgs& a, LaunchCfg lc, int K, int D, int rain, const void* U,
+                      const double* auxT, const double* auxS, const void* lam, void* out,
+                      const void* X1, const void* X2, const double* dt, double cx1, double cx2,
+                      double c1, double c2, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      hipLaunchKernelGGL((rhs_vjp_kernel<R, K_, D_, R_>), dim3(grid_for_items(a.nitems)),
-                         dim3(Shape<K_, D_>::NT), 0, s, a, (const R*)U, auxT, auxS, (const R*)lam,
+      hipLaunchKernelGGL((rhs_vjp_kernel<R, K_, D_, R_>), dim3(lc.grid), dim3(lc.threads), 0, s, a, (const R*)U, auxT, auxS, (const R*)lam,
                          (R*)out, (const R*)X1, (const R*)X2, dt, cx1, cx2, c1, c2);
     });
   }
 
-  static bool split_vjp(const KArgs& a, int K, int D, int rain, const void* U, const double* auxT,
-                        const double* auxS, const double* Tb, const double* rvb,
+  static bool split_vjp(const KArgs& a, LaunchCfg lc, int K, int D, int rain, const void* U,
+                        const double* auxT, const double* auxS, const double* Tb, const double* rvb,
                         const double* rcb, void* out, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      hipLaunchKernelGGL((split_vjp_kernel<R, K_, D_, R_>), dim3(grid_for_items(a.nitems)),
-                         dim3(Shape<K_, D_>::NT), 0, s, a, (const R*)U, auxT, auxS, Tb, rvb, rcb,
+      hipLaunchKernelGGL((split_vjp_kernel<R, K_, D_, R_>), dim3(lc.grid), dim3(lc.threads), 0, s, a, (const R*)U, auxT, auxS, Tb, rvb, rcb,
                          (R*)out);
     });
   }

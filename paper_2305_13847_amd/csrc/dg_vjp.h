@@ -326,13 +326,17 @@ rhs_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT
                double cx1, double cx2, double c1, double c2) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
-  constexpr int P1 = S::P1, NP = S::NP, NV = V::NV, NT = S::NT;
-  __shared__ R sL[NV * NT];
+  constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
+  __shared__ R sL[NV * S::NT];
   __shared__ R sD[P1 * P1];
-  const int it_ = item_of_block(a.nitems);
-  if (it_ >= a.nitems) return;
+  const int NT = blockDim.x;
   const int t = threadIdx.x;
   if (t < P1 * P1) sD[t] = (R)a.Dhat[t];
+  const ItemWalk walk(a.nitems);
+  for (int kk = 0;; ++kk) {
+  const int it_ = walk.item(kk);
+  if (it_ < 0) break;
+  __syncthreads();   // sL of the previous item is no longer read
   const int2 item = a.items[it_];
   const MemberDesc& md = a.mem[item.x];
   const int le = t / NP, n = t - le * NP;
@@ -363,7 +367,7 @@ rhs_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT
 #pragma unroll
   for (int v = 0; v < NV; ++v) sL[v * NT + t] = Lq[v];
   __syncthreads();
-  if (!active) return;
+  if (!active) continue;
   Pt<R, D, RAIN> q;
   eval_point<R, D, RAIN>(a, Uq, T, rvs, iz, q);
   PwSeed<D, RAIN> sd;
@@ -431,6 +435,7 @@ rhs_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT
     if (X2) o += cx2 * (double)X2[v * N + g];
     out[v * N + g] = (R)o;
   }
+  }
 }
 
 // adjoint of the split alone: (T_bar, rho_v_bar, rho_c_bar) -> U_bar
@@ -443,14 +448,16 @@ split_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ au
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
-  const int it_ = item_of_block(a.nitems);
-  if (it_ >= a.nitems) return;
+  const ItemWalk walk(a.nitems);
+  for (int kk = 0;; ++kk) {
+  const int it_ = walk.item(kk);
+  if (it_ < 0) break;
   const int t = threadIdx.x;
   const int2 item = a.items[it_];
   const MemberDesc& md = a.mem[item.x];
   const int le = t / NP, n = t - le * NP;
   const int e = item.y + le;
-  if (e >= md.ne) return;
+  if (e >= md.ne) continue;
   const long long N = a.etot * NP;
   const long long g = (md.eoff + e) * NP + n;
   const ElemCoord<D> ec = elem_coord<D>(md, e);
@@ -486,6 +493,7 @@ split_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ au
   Ub[V::E] = reb;
 #pragma unroll
   for (int v = 0; v < NV; ++v) out[v * N + g] = (R)Ub[v];
+  }
 }
 
 }  // namespace dgm

@@ -53,7 +53,7 @@ EXPORTS = ["dg_default_params", "dg_create", "dg_create_batch", "dg_set_backgrou
            "dg_member_offset", "dg_state_size", "dg_rhs", "dg_saturation_split", "dg_rk_step",
            "dg_rhs_vjp", "dg_saturation_split_vjp", "dg_rk_step_vjp", "dg_reduce_mass",
            "dg_get_stats", "dg_reset_stats", "dg_destroy", "dg_last_error", "dg_timing_enable",
-           "dg_timing_read"]
+           "dg_timing_read", "dg_set_launch", "dg_get_launch", "dg_autotune", "dg_rk_step_graph"]
 DG_K_SPLIT, DG_K_STAGE, DG_K_ADJOINT, DG_K_OTHER = 0, 1, 2, 3
 
 _lib = None
@@ -89,6 +89,10 @@ def load(path: str = LIB_PATH):
     L.dg_destroy.argtypes = [vp]
     L.dg_timing_enable.argtypes = [vp, ct.c_int]
     L.dg_timing_read.argtypes = [vp, ct.c_int, dp, ct.POINTER(ct.c_longlong)]
+    L.dg_set_launch.argtypes = [vp, ct.c_int, ct.c_int]
+    L.dg_get_launch.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
+    L.dg_autotune.argtypes = [vp, vp, dp, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), dp]
+    L.dg_rk_step_graph.argtypes = [vp, vp, dp, ct.c_int, vp]
     L.dg_last_error.argtypes = []
     L.dg_last_error.restype = ct.c_char_p
     for name in EXPORTS:
@@ -223,6 +227,47 @@ class DG:
         _check(self.L.dg_rk_step(self.h, self._state(U), dts.ctypes.data_as(ct.POINTER(ct.c_double)),
                                  int(nsteps), ct.c_void_p(_stream(stream))))
         return U
+
+    def rk_step_graph(self, U, dt, nsteps: int = 1, stream=None):
+        dts = np.ascontiguousarray(np.atleast_1d(np.asarray(dt, dtype=np.float64)))
+        if dts.size != len(self.meshes):
+            raise ValueError("dt needs %d values" % len(self.meshes))
+        _check(self.L.dg_rk_step_graph(self.h, self._state(U), dts.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                       int(nsteps), ct.c_void_p(_stream(stream))))
+        return U
+
+    def set_launch(self, elems_per_block: int, persist_per_cu: int):
+        _check(self.L.dg_set_launch(self.h, int(elems_per_block), int(persist_per_cu)))
+
+    def get_launch(self):
+        e, p = ct.c_int(), ct.c_int()
+        _check(self.L.dg_get_launch(self.h, ct.byref(e), ct.byref(p)))
+        return e.value, p.value
+
+    def autotune(self, U, dt, nsteps: int = 3, cache: Optional[str] = None, key: Optional[str] = None):
+        """Pick elements per block and the persistent grid by timing; optional JSON cache."""
+        import json
+        if cache and key and os.path.exists(cache):
+            with open(cache) as f:
+                rec = json.load(f).get(key)
+            if rec:
+                self.set_launch(rec["elems_per_block"], rec["persist_per_cu"])
+                return rec
+        dts = np.ascontiguousarray(np.atleast_1d(np.asarray(dt, dtype=np.float64)))
+        e, p, ms = ct.c_int(), ct.c_int(), ct.c_double()
+        _check(self.L.dg_autotune(self.h, self._state(U), dts.ctypes.data_as(ct.POINTER(ct.c_double)),
+                                  int(nsteps), ct.byref(e), ct.byref(p), ct.byref(ms)))
+        rec = dict(elems_per_block=e.value, persist_per_cu=p.value, ms_per_step=ms.value)
+        if cache and key:
+            data = {}
+            if os.path.exists(cache):
+                with open(cache) as f:
+                    data = json.load(f)
+            data[key] = rec
+            os.makedirs(os.path.dirname(os.path.abspath(cache)), exist_ok=True)
+            with open(cache, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+        return rec
 
     def rhs_vjp(self, U, lam, out=None, stream=None):
         import torch
