@@ -82,6 +82,32 @@ def time_workload(case, precision, steps, warmup, lib, torch, kernel_timing=True
     return out
 
 
+def time_ensemble(steps, lib, torch, synth):
+    """64 uneven 2D bubbles (Q3, 5 vars) in one handle, FP32 bulk, hipGraph replay, autotuned."""
+    cases = synth.ensemble(nmembers=64, order=3, nsteps=steps)
+    dts = np.array([c.dt for c in cases])
+    dg = lib.for_ensemble(cases, precision=lib.DG_FP32_BULK)
+    U = torch.cat([torch.tensor(c.U, dtype=torch.float32).reshape(c.nvars, -1) for c in cases],
+                  dim=1).contiguous().cuda().reshape(dg.shape)
+    dofs = sum(c.U.size for c in cases)
+    tune = dg.autotune(U, dts, nsteps=2)
+    dg.rk_step_graph(U, dts, steps)          # capture + first replay
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dg.rk_step_graph(U, dts, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dg.rk_step(U, dts, steps)                # eager, for comparison
+    torch.cuda.synchronize()
+    el_eager = time.perf_counter() - t0
+    st = dg.stats()
+    dg.close()
+    return {"dof_stage_per_s": dofs * 4 * steps / el, "ms_per_step": 1e3 * el / steps,
+            "eager_ms_per_step": 1e3 * el_eager / steps, "members": len(cases), "dofs": dofs,
+            "elements": sum(c.mesh.ne for c in cases), "launch": tune, "status": st["status"]}
+
+
 def cpu_baseline(synth, oracle_mod):
     """FP64 reference, one RK step on a 16 x 16 x 32 column sample of the 3D case."""
     import multiprocessing
@@ -103,7 +129,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
+                    help="only copy a device buffer of this size (traffic-counter calibration)")
     args = ap.parse_args()
+    if args.copy_only:
+        import torch
+        a = torch.ones(args.copy_only * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": args.copy_only, "launches": 3}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the single-GPU kernel is the product here; "
               "multi-GPU runs are not part of this build (requested --gpus %d)" % args.gpus,
@@ -129,9 +166,12 @@ def main():
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic_for("stage", "rain-3d-q3-64x64x32-fp32"),
             "kernel": "rhs_kernel<float,3,3,rain,stage>", "kernel_us": res["stage_us"],
-            "split_kernel_us": res["split_us"],
             "alg_bytes_per_launch": alg_stage,
-            "whole_stage_frac": alg_stage / ((res["stage_us"] + res["split_us"]) * 1e-6) / 1e9 / HBM_PEAK_GBS}
+            # the stand-alone split runs once per dg_rk_step call (the fused stage
+            # kernels split every later stage state); the step-level fraction
+            # counts everything between the synchronisations
+            "call_split_kernel_us": res["split_us"],
+            "step_level_frac": 4 * alg_stage / (res["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
     extra = {}
     if not args.no_extra:
@@ -142,6 +182,7 @@ def main():
         for prec, nm in ((lib.DG_FP64, "bubble2d_q4_fp64"), (lib.DG_FP32_BULK, "bubble2d_q4_fp32")):
             r = time_workload(bub, prec, 50, 5, lib, torch)
             extra[nm] = {k: r[k] for k in ("dof_stage_per_s", "ms_per_step", "stage_us", "split_us")}
+        extra["ensemble64_q3_fp32_graph"] = time_ensemble(20, lib, torch, synth)
     cpu = None
     if not args.no_cpu:
         import oracle as oracle_mod

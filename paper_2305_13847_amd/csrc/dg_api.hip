@@ -54,7 +54,7 @@ struct dg_handle {
   int dim = 0, order = 0, nvars = 0, rain = 0, prec = 0, rk = 0, nmembers = 0;
   dg_params P{};
   std::vector<MemberDesc> mem;
-  std::vector<int2> items;
+  std::vector<Item> items;
   std::vector<int> item_off;     // first item of each member (+ total)
   std::vector<int> hoff;         // first background index of each member (+ total)
   std::vector<char> bg_set;
@@ -63,7 +63,7 @@ struct dg_handle {
   size_t state_bytes = 0;
   // device
   MemberDesc* mem_d = nullptr;
-  int2* items_d = nullptr;
+  Item* items_d = nullptr;
   double* bg_d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // rd, rm, rr, E, p
   void* stage[2] = {nullptr, nullptr};
   void* stage_x[4] = {nullptr, nullptr, nullptr, nullptr};          // adjoint workspace
@@ -204,7 +204,8 @@ static void free_all(dg_handle* h) {
 static dg_status validate_mesh(const dg_mesh* m, int dim) {
   if (m->dim != dim) return fail(DG_EINVAL, "all members must have the same dimension");
   for (int a = 0; a < dim; ++a) {
-    if (m->n[a] < 1 || m->n[a] > (1 << 20)) return fail(DG_EINVAL, "mesh.n[%d] = %d out of range", a, m->n[a]);
+    if (m->n[a] < 1 || m->n[a] > (a == 0 ? (1 << 20) : 32767))
+      return fail(DG_EINVAL, "mesh.n[%d] = %d out of range", a, m->n[a]);
     if (!(m->hi[a] > m->lo[a])) return fail(DG_EINVAL, "mesh.hi[%d] must exceed mesh.lo[%d]", a, a);
     if (m->bc[a] != DG_PERIODIC && m->bc[a] != DG_SLIPWALL)
       return fail(DG_EINVAL, "mesh.bc[%d] must be DG_PERIODIC or DG_SLIPWALL", a);
@@ -218,7 +219,18 @@ static void build_items(dg_handle* h, int epb) {
   h->item_off.clear();
   for (int m = 0; m < h->nmembers; ++m) {
     h->item_off.push_back((int)h->items.size());
-    for (int e0 = 0; e0 < h->mem[m].ne; e0 += epb) h->items.push_back(make_int2(m, e0));
+    const MemberDesc& md = h->mem[m];
+    for (int e0 = 0; e0 < md.ne; e0 += epb) {
+      Item it;
+      it.member = m;
+      it.e0 = e0;
+      it.c0 = e0 % md.n[0];
+      const int row = e0 / md.n[0];
+      const int c1 = row % md.n[1];
+      const int c2 = row / md.n[1];
+      it.c12 = c1 + (c2 << 16);
+      h->items.push_back(it);
+    }
   }
   h->item_off.push_back((int)h->items.size());
   h->epb = epb;
@@ -303,6 +315,10 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   h->bg_set.assign(nmembers, 0);
   h->etot = eoff;
   h->nnodes = eoff * h->np;
+  if (h->nnodes >= (1LL << 31)) {
+    delete h;
+    return fail(DG_EINVAL, "a handle holds at most 2^31 - 1 nodes");
+  }
   const size_t rsz = h->prec == DG_FP64 ? sizeof(double) : sizeof(float);
   h->state_bytes = (size_t)nvars * h->nnodes * rsz;
 
@@ -310,7 +326,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   auto A = [&](void** ptr, size_t bytes) -> bool { return hipMalloc(ptr, bytes) == hipSuccess; };
   bool ok = true;
   ok = ok && A((void**)&h->mem_d, sizeof(MemberDesc) * nmembers);
-  ok = ok && A((void**)&h->items_d, sizeof(int2) * h->items_cap);
+  ok = ok && A((void**)&h->items_d, sizeof(Item) * h->items_cap);
   for (auto& b : h->bg_d) ok = ok && A((void**)&b, sizeof(double) * hoff);
   for (auto& b : h->stage) ok = ok && A(&b, h->state_bytes);
   ok = ok && A((void**)&h->auxT, sizeof(double) * h->nnodes);
@@ -335,7 +351,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
     return fail(DG_ENOMEM, "device allocation failed (state of %zu bytes)", sb);
   }
   if (hipMemcpy(h->mem_d, h->mem.data(), sizeof(MemberDesc) * nmembers, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(h->items_d, h->items.data(), sizeof(int2) * h->items.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(h->items_d, h->items.data(), sizeof(Item) * h->items.size(), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemset(h->stats, 0, sizeof(unsigned) * 8) != hipSuccess ||
       hipMemset(h->auxT, 0, sizeof(double) * h->nnodes) != hipSuccess ||
       hipMemset(h->auxS, 0, sizeof(double) * h->nnodes) != hipSuccess) {
@@ -366,6 +382,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   a.nitems = (int)h->items.size();
   a.nmembers = nmembers;
   a.etot = h->etot;
+  a.nnodes = (unsigned)h->nnodes;
   a.bg_rd = h->bg_d[0]; a.bg_rm = h->bg_d[1]; a.bg_rr = h->bg_d[2]; a.bg_E = h->bg_d[3];
   a.bg_p = h->bg_d[4];
   a.stats = h->stats;
@@ -504,7 +521,7 @@ static dg_status upload_dt(dg_handle* h, const double* dt, hipStream_t s) {
 // fused stage kernel also splits the state it writes, so the next stage reads
 // (T, rho_vs) from the ping-pong aux buffers; only the first stage of a call
 // runs the stand-alone split.  *cur is the aux buffer holding the split of U.
-static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t s) {
+static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t s, int step = 0) {
   void* B1 = h->stage[0];
   void* B2 = h->stage[1];
   double* aT[2] = {h->auxT, h->auxT2};
@@ -523,7 +540,9 @@ static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t
     const void* in = h->rk == DG_SSPRK43 ? in43[st] : in33[st];
     void* outp = h->rk == DG_SSPRK43 ? out43[st] : out33[st];
     const int a = *cur, b = 1 - *cur;
-    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], st == ns - 1);
+    // the stored rho_vs(T) anchors the next split; it is evaluated afresh at
+    // the last stage of every fourth step so series updates never chain long
+    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], st == ns - 1 && (step & 3) == 3);
     *cur = b;
   }
   HIP_TRY(hipGetLastError());
@@ -539,7 +558,7 @@ extern "C" dg_status dg_rk_step(dg_handle* h, void* U, const double* dt, int nst
   if (st != DG_OK) return st;
   int cur = 0;
   for (int i = 0; i < nsteps; ++i) {
-    st = rk_one(h, U, i == 0, &cur, s);
+    st = rk_one(h, U, i == 0, &cur, s, i);
     if (st != DG_OK) return st;
   }
   return DG_OK;
@@ -719,7 +738,7 @@ extern "C" dg_status dg_timing_read(dg_handle* h, int kclass, double* total_ms, 
 }
 
 static dg_status upload_items(dg_handle* h) {
-  HIP_TRY(hipMemcpy(h->items_d, h->items.data(), sizeof(int2) * h->items.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->items_d, h->items.data(), sizeof(Item) * h->items.size(), hipMemcpyHostToDevice));
   h->ka.nitems = (int)h->items.size();
   return DG_OK;
 }
@@ -777,7 +796,7 @@ extern "C" dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, 
       rk_one(h, W, true, &cur, 0);                       // warm-up
       HIP_TRY(hipMemcpy(W, U, h->state_bytes, hipMemcpyDeviceToDevice));
       HIP_TRY(hipEventRecord(e0, 0));
-      for (int i = 0; i < nsteps; ++i) rk_one(h, W, i == 0, &cur, 0);
+      for (int i = 0; i < nsteps; ++i) rk_one(h, W, i == 0, &cur, 0, i);
       HIP_TRY(hipEventRecord(e1, 0));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;
@@ -814,7 +833,7 @@ extern "C" dg_status dg_rk_step_graph(dg_handle* h, void* U, const double* dt, i
     HIP_TRY(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
     int cur = 0;
     dg_status cs = DG_OK;
-    for (int i = 0; i < nsteps && cs == DG_OK; ++i) cs = rk_one(h, U, i == 0, &cur, h->cap_stream);
+    for (int i = 0; i < nsteps && cs == DG_OK; ++i) cs = rk_one(h, U, i == 0, &cur, h->cap_stream, i);
     hipGraph_t g = nullptr;
     hipError_t ce = hipStreamEndCapture(h->cap_stream, &g);
     if (cs != DG_OK) { if (g) (void)hipGraphDestroy(g); return cs; }

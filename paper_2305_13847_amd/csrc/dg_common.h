@@ -22,6 +22,15 @@ struct MemberDesc {
   int hoff;             // first background index (n_z (k+1) entries)
 };
 
+// A work item: EPB consecutive elements of one member, starting at element e0
+// with element coordinates (c0, c1, c2) packed as c12 = c1 + (c2 << 16).
+struct Item {
+  int member;
+  int e0;
+  int c0;
+  int c12;
+};
+
 // Everything the kernels need besides the state arrays.
 struct KArgs {
   // thermodynamics (Section 2; appendix table)
@@ -37,10 +46,11 @@ struct KArgs {
   double w[kMaxP1];
   // members and work items (member, first element) of EPB elements each
   const MemberDesc* mem;
-  const int2* items;
+  const Item* items;
   int nitems;
   int nmembers;
-  long long etot;                  // elements of all members (variable stride / np)
+  long long etot;                  // elements of all members
+  unsigned nnodes;                 // nodes of all members: the stride between variables
   // background per vertical node index, concatenated over members
   const double* bg_rd;
   const double* bg_rm;

@@ -103,8 +103,11 @@ __device__ __forceinline__ double rcp64(double v) {
 // The Newton step uses the hardware reciprocal of f' (relative error far
 // below the step's own size, so convergence stays quadratic).  Stopping:
 // |dT| <= rtol T, or, above 150 K, the quadratic-convergence bound: after a
-// step dT the error is at most M dT^2 with M = max |f''| / (2 min f') < 1 K^-1,
-// so |dT| <= sqrt(rtol T / M) already leaves an error below rtol T.
+// step dT the error is at most M dT^2 with M = max |f''| / (2 min f').  With
+// f' >= rho_vs' L_eff and f'' <= rho_vs'' L_eff (the c_vv - c_l term is below
+// 2e-3 of it), M <= (q + q'/q)/2 + 2e-3 with q = d ln rho_vs / dT, which is
+// 0.15 K^-1 at 150 K and falls with T; M = 0.25 K^-1 is used, so
+// |dT| <= sqrt(rtol T / M) already leaves an error below rtol T.
 // If `A` holds a valid anchor (A.T0 > 0) it is used and updated in place.
 struct NewtonOut {
   double T, rvs;
@@ -117,7 +120,7 @@ __device__ __forceinline__ NewtonOut newton_sat(const KArgs& a, double Cu, doubl
   const double dc = a.cvv - a.cl;
   if (!(A.T0 > 0.0) || !in_anchor(A, T)) A = make_anchor(a, T);
   const double tol_lin = a.rtol * T;
-  const double tol = T > 150.0 ? fmax(tol_lin, sqrt(tol_lin)) : tol_lin;
+  const double tol = T > 150.0 ? fmax(tol_lin, 2.0 * sqrt(tol_lin)) : tol_lin;
   NewtonOut o;
   o.state = 2;
   double rvs = 0.0;

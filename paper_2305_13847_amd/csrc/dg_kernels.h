@@ -15,16 +15,20 @@ struct ElemCoord {
   int c[3];
 };
 
+// Coordinates of element e0 + le of a work item (items may run past the end of
+// an x-row; the carry moves to the next row).
 template <int D>
-__device__ __forceinline__ ElemCoord<D> elem_coord(const MemberDesc& md, int e) {
+__device__ __forceinline__ ElemCoord<D> item_coord(const MemberDesc& md, const Item& it, int le) {
   ElemCoord<D> ec;
-  ec.c[0] = e % md.n[0];
-  if (D == 2) {
-    ec.c[1] = e / md.n[0];
-    ec.c[2] = 0;
-  } else {
-    ec.c[1] = (e / md.n[0]) % md.n[1];
-    ec.c[2] = e / (md.n[0] * md.n[1]);
+  ec.c[0] = it.c0 + le;
+  ec.c[1] = it.c12 & 0xffff;
+  ec.c[2] = it.c12 >> 16;
+  while (ec.c[0] >= md.n[0]) {
+    ec.c[0] -= md.n[0];
+    if (++ec.c[1] >= md.n[1] && D == 3) {
+      ec.c[1] = 0;
+      ++ec.c[2];
+    }
   }
   return ec;
 }
@@ -73,21 +77,21 @@ split_kernel(KArgs a, int item0, int nitems, const R* __restrict__ U, const doub
   const int it_ = walk.item(k);
   if (it_ < 0) break;
   const int t = threadIdx.x;
-  const int2 item = a.items[item0 + it_];
-  const MemberDesc& md = a.mem[item.x];
+  const Item item = a.items[item0 + it_];
+  const MemberDesc& md = a.mem[item.member];
   const int le = t / NP, n = t - le * NP;
-  const int e = item.y + le;
+  const int e = item.e0 + le;
   const bool active = e < md.ne;
   int iters = 0, bad = 0;
   if (active) {
-    const long long N = a.etot * NP;
-    const long long g = (md.eoff + e) * NP + n;
-    const ElemCoord<D> ec = elem_coord<D>(md, e);
+    const unsigned N = a.nnodes;
+    const unsigned g = (unsigned)(md.eoff + e) * NP + n;
+    const ElemCoord<D> ec = item_coord<D>(md, item, le);
     const int l = (D == 2) ? n / P1 : n / (P1 * P1);
     const int iz = md.hoff + ec.c[D - 1] * P1 + l;
     R Uq[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Uq[v] = U[v * N + g];
+    for (int v = 0; v < NV; ++v) Uq[v] = (U + (size_t)v * N)[g];
     const double rd = a.bg_rd[iz] + (double)Uq[V::RD];
     const double rm = a.bg_rm[iz] + (double)Uq[V::RM];
     const double rr = RAIN ? a.bg_rr[iz] + (double)Uq[V::RR] : 0.0;
@@ -136,7 +140,7 @@ template <typename R, int K, int D, int RAIN, int J>
 __device__ __forceinline__ void gather_nb(const MemberDesc& md, const ElemCoord<D>& ec, int e, int n,
                                           int ij, const R* __restrict__ U,
                                           const double* __restrict__ auxT,
-                                          const double* __restrict__ auxS, long long N,
+                                          const double* __restrict__ auxS, unsigned N,
                                           Nb<R, D, RAIN>& nb, bool& wall, int& izn_off) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
@@ -152,9 +156,9 @@ __device__ __forceinline__ void gather_nb(const MemberDesc& md, const ElemCoord<
   if (cn >= md.n[J]) cn -= md.n[J];
   const int en = e + (cn - c) * elem_stride(md, J);
   const int nn = plus ? n - K * STR : n + K * STR;
-  const long long gn = (md.eoff + en) * (long long)S::NP + nn;
+  const unsigned gn = (unsigned)(md.eoff + en) * S::NP + nn;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) nb.U[v] = U[v * N + gn];
+  for (int v = 0; v < NV; ++v) nb.U[v] = (U + (size_t)v * N)[gn];
   nb.T = auxT[gn];
   nb.rvs = auxS[gn];
   izn_off = (J == D - 1) ? (cn * P1 + (plus ? 0 : K)) : -1;
@@ -238,30 +242,25 @@ __device__ __forceinline__ void face_dir(const KArgs& a, const MemberDesc& md, i
 }
 
 template <typename R, int K, int D, int RAIN, int MODE>
-__global__ void __launch_bounds__(256)
-rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
-           const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
-           const double* __restrict__ dt_m, double c0, double c1, double c2,
-           double* __restrict__ oT, double* __restrict__ oS, int refresh) {
+__device__ __forceinline__ void rhs_item(const KArgs& a, int it_, R (*sF)[Vars<D, RAIN>::NV * Shape<K, D>::NT],
+                                         const R* sD, const R* __restrict__ U,
+                                         const double* __restrict__ auxT,
+                                         const double* __restrict__ auxS, R* __restrict__ out,
+                                         const R* __restrict__ U0, const double* __restrict__ dt_m,
+                                         double c0, double c1, double c2, double* __restrict__ oT,
+                                         double* __restrict__ oS, int refresh) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
-  __shared__ R sF[D][NV * S::NT];
-  __shared__ R sD[P1 * P1];
   const int t = threadIdx.x;
-  if (t < P1 * P1) sD[t] = (R)a.Dhat[t];
-  const ItemWalk walk(a.nitems);
-  for (int kk = 0;; ++kk) {
-  const int it_ = walk.item(kk);
-  if (it_ < 0) break;
-  const int2 item = a.items[it_];
-  const MemberDesc& md = a.mem[item.x];
+  const Item item = a.items[it_];
+  const MemberDesc& md = a.mem[item.member];
   const int le = t / NP, n = t - le * NP;
-  const int e = item.y + le;
+  const int e = item.e0 + le;
   const bool active = e < md.ne;
-  const long long N = a.etot * NP;
-  const long long g = (md.eoff + (active ? e : 0)) * NP + n;
-  const ElemCoord<D> ec = elem_coord<D>(md, active ? e : 0);
+  const unsigned N = a.nnodes;
+  const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
+  const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
   int idx[3];
   idx[0] = n % P1;
   idx[1] = (n / P1) % P1;
@@ -271,7 +270,7 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   double T = 300.0, rvs = 0.0;
   if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Uq[v] = U[v * N + g];
+    for (int v = 0; v < NV; ++v) Uq[v] = (U + (size_t)v * N)[g];
     T = auxT[g];
     rvs = auxS[g];
   } else {
@@ -314,21 +313,21 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
     sources<R, D, RAIN>(a, Uq, q, Rv);
     if (MODE == 0) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) out[v * N + g] = Rv[v];
+      for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = Rv[v];
     } else {
-      const R k2 = (R)(c2 * dt_m[item.x]);
+      const R k2 = (R)(c2 * dt_m[item.member]);
       const R k1 = (R)c1;
       R Un[NV];
       if (c0 != 0.0) {
         const R k0 = (R)c0;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Un[v] = k0 * U0[v * N + g] + k1 * Uq[v] + k2 * Rv[v];
+        for (int v = 0; v < NV; ++v) Un[v] = k0 * (U0 + (size_t)v * N)[g] + k1 * Uq[v] + k2 * Rv[v];
       } else {
 #pragma unroll
         for (int v = 0; v < NV; ++v) Un[v] = k1 * Uq[v] + k2 * Rv[v];
       }
 #pragma unroll
-      for (int v = 0; v < NV; ++v) out[v * N + g] = Un[v];
+      for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = Un[v];
       if (MODE == 2) {
         // split of the new state (FP64), warm-started at this node's (T, rho_vs)
         const double rd = a.bg_rd[iz] + (double)Un[V::RD];
@@ -356,9 +355,50 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
     }
   }
   if (MODE == 2) record_stats(a, iters, bad);
-  __syncthreads();   // sF is reused by the next item
+}
+
+// one work item per block
+template <typename R, int K, int D, int RAIN, int MODE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
+           const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
+           const double* __restrict__ dt_m, double c0, double c1, double c2,
+           double* __restrict__ oT, double* __restrict__ oS, int refresh) {
+  using S = Shape<K, D>;
+  using V = Vars<D, RAIN>;
+  constexpr int P1 = S::P1;
+  __shared__ R sF[D][V::NV * S::NT];
+  __shared__ R sD[P1 * P1];
+  if (threadIdx.x < P1 * P1) sD[threadIdx.x] = (R)a.Dhat[threadIdx.x];
+  const ItemWalk walk(a.nitems);
+  const int it_ = walk.item(0);
+  if (it_ < 0) return;
+  rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
+}
+
+// persistent: a grid smaller than the item count walks the items
+template <typename R, int K, int D, int RAIN, int MODE>
+__global__ void __launch_bounds__(256)
+rhs_kernel_persistent(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
+                      const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
+                      const double* __restrict__ dt_m, double c0, double c1, double c2,
+                      double* __restrict__ oT, double* __restrict__ oS, int refresh) {
+  using S = Shape<K, D>;
+  using V = Vars<D, RAIN>;
+  constexpr int P1 = S::P1;
+  __shared__ R sF[D][V::NV * S::NT];
+  __shared__ R sD[P1 * P1];
+  if (threadIdx.x < P1 * P1) sD[threadIdx.x] = (R)a.Dhat[threadIdx.x];
+  const ItemWalk walk(a.nitems);
+  for (int kk = 0;; ++kk) {
+    const int it_ = walk.item(kk);
+    if (it_ < 0) break;
+    rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
+    __syncthreads();   // sF is reused by the next item
   }
 }
+
+
 
 // ---------------------------------------------------------------------------
 // conservation diagnostics: per-block FP64 partial sums in a fixed order
@@ -373,14 +413,14 @@ mass_kernel(KArgs a, int item0, const R* __restrict__ U, double* __restrict__ pa
   __shared__ double sm[3][S::NT];
   const int NT = blockDim.x;
   const int t = threadIdx.x;
-  const int2 item = a.items[item0 + blockIdx.x];
-  const MemberDesc& md = a.mem[item.x];
+  const Item item = a.items[item0 + blockIdx.x];
+  const MemberDesc& md = a.mem[item.member];
   const int le = t / NP, n = t - le * NP;
-  const int e = item.y + le;
+  const int e = item.e0 + le;
   double md_ = 0.0, mw = 0.0, fl = 0.0;
   if (e < md.ne) {
-    const long long N = a.etot * NP;
-    const long long g = (md.eoff + e) * NP + n;
+    const size_t N = a.nnodes;
+    const size_t g = (size_t)(md.eoff + e) * NP + n;
     int idx[3] = {n % P1, (n / P1) % P1, (D == 3) ? n / (P1 * P1) : 0};
     double w = md.J;
 #pragma unroll
@@ -388,7 +428,7 @@ mass_kernel(KArgs a, int item0, const R* __restrict__ U, double* __restrict__ pa
     md_ = w * (double)U[V::RD * N + g];
     mw = w * ((double)U[V::RM * N + g] + (RAIN ? (double)U[V::RR * N + g] : 0.0));
     if (RAIN && md.bc[D - 1] == 1) {
-      const ElemCoord<D> ec = elem_coord<D>(md, e);
+      const ElemCoord<D> ec = item_coord<D>(md, item, le);
       const int l = idx[D - 1];
       const bool bottom = ec.c[D - 1] == 0 && l == 0;
       const bool top = ec.c[D - 1] == md.n[D - 1] - 1 && l == K;

@@ -68,12 +68,15 @@ struct Launch {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
       dim3 grid(lc.grid), block(lc.threads);
-#define DGM_RHS(M)                                                                                \
-  hipLaunchKernelGGL((rhs_kernel<R, K_, D_, R_, M>), grid, block, 0, s, a, (const R*)U, auxT, auxS, \
+#define DGM_RHS(KER, M)                                                                           \
+  hipLaunchKernelGGL((KER<R, K_, D_, R_, M>), grid, block, 0, s, a, (const R*)U, auxT, auxS,       \
                      (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, refresh)
-      if (mode == 0) DGM_RHS(0);
-      else if (mode == 1) DGM_RHS(1);
-      else DGM_RHS(2);
+      // the persistent (looping) variant only when the grid is smaller than the items
+      const bool persist = (int)grid.x < grid_for_items(a.nitems);
+      if (mode == 0) DGM_RHS(rhs_kernel, 0);
+      else if (mode == 1) DGM_RHS(rhs_kernel, 1);
+      else if (!persist) DGM_RHS(rhs_kernel, 2);
+      else DGM_RHS(rhs_kernel_persistent, 2);
 #undef DGM_RHS
     });
   }

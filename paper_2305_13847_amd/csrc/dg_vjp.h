@@ -337,14 +337,14 @@ rhs_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT
   const int it_ = walk.item(kk);
   if (it_ < 0) break;
   __syncthreads();   // sL of the previous item is no longer read
-  const int2 item = a.items[it_];
-  const MemberDesc& md = a.mem[item.x];
+  const Item item = a.items[it_];
+  const MemberDesc& md = a.mem[item.member];
   const int le = t / NP, n = t - le * NP;
-  const int e = item.y + le;
+  const int e = item.e0 + le;
   const bool active = e < md.ne;
-  const long long N = a.etot * NP;
-  const long long g = (md.eoff + (active ? e : 0)) * NP + n;
-  const ElemCoord<D> ec = elem_coord<D>(md, active ? e : 0);
+  const unsigned N = a.nnodes;
+  const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
+  const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
   int idx[3];
   idx[0] = n % P1;
   idx[1] = (n / P1) % P1;
@@ -355,8 +355,8 @@ rhs_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT
   if (active) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      Uq[v] = U[v * N + g];
-      Lq[v] = lam[v * N + g];
+      Uq[v] = (U + (size_t)v * N)[g];
+      Lq[v] = (lam + (size_t)v * N)[g];
     }
     T = auxT[g];
     rvs = auxS[g];
@@ -411,9 +411,9 @@ rhs_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT
       if (cn >= md.n[J]) cn -= md.n[J];
       const int en = e + (cn - ec.c[J]) * elem_stride(md, J);
       const int nn = plus ? n - K * str : n + K * str;
-      const long long gn = (md.eoff + en) * (long long)NP + nn;
+      const unsigned gn = (unsigned)(md.eoff + en) * NP + nn;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Ln[v] = lam[v * N + gn];
+      for (int v = 0; v < NV; ++v) Ln[v] = (lam + (size_t)v * N)[gn];
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) Ln[v] = R(0);
@@ -427,13 +427,13 @@ rhs_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT
   for (int v = 0; v < NV; ++v) sd.G[v] = (double)Lq[v];
   pointwise_vjp<R, D, RAIN>(a, Uq, T, rvs, iz, sd, Ub);
   // out = cx1 X1 + cx2 X2 + c1 lam + c2 dt (d rhs/dU)^T lam
-  const double k2 = c2 * (dt_m ? dt_m[item.x] : 1.0);
+  const double k2 = c2 * (dt_m ? dt_m[item.member] : 1.0);
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     double o = c1 * (double)Lq[v] + k2 * Ub[v];
-    if (X1) o += cx1 * (double)X1[v * N + g];
-    if (X2) o += cx2 * (double)X2[v * N + g];
-    out[v * N + g] = (R)o;
+    if (X1) o += cx1 * (double)(X1 + (size_t)v * N)[g];
+    if (X2) o += cx2 * (double)(X2 + (size_t)v * N)[g];
+    (out + (size_t)v * N)[g] = (R)o;
   }
   }
 }
@@ -453,19 +453,19 @@ split_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ au
   const int it_ = walk.item(kk);
   if (it_ < 0) break;
   const int t = threadIdx.x;
-  const int2 item = a.items[it_];
-  const MemberDesc& md = a.mem[item.x];
+  const Item item = a.items[it_];
+  const MemberDesc& md = a.mem[item.member];
   const int le = t / NP, n = t - le * NP;
-  const int e = item.y + le;
+  const int e = item.e0 + le;
   if (e >= md.ne) continue;
-  const long long N = a.etot * NP;
-  const long long g = (md.eoff + e) * NP + n;
-  const ElemCoord<D> ec = elem_coord<D>(md, e);
+  const unsigned N = a.nnodes;
+  const unsigned g = (unsigned)(md.eoff + e) * NP + n;
+  const ElemCoord<D> ec = item_coord<D>(md, item, le);
   const int l = (D == 2) ? n / P1 : n / (P1 * P1);
   const int iz = md.hoff + ec.c[D - 1] * P1 + l;
   double Uq[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) Uq[v] = (double)U[v * N + g];
+  for (int v = 0; v < NV; ++v) Uq[v] = (double)(U + (size_t)v * N)[g];
   const double rd = a.bg_rd[iz] + Uq[V::RD];
   const double rm = a.bg_rm[iz] + Uq[V::RM];
   const double rr = RAIN ? a.bg_rr[iz] + Uq[V::RR] : 0.0;
@@ -492,7 +492,7 @@ split_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ au
   for (int i = 0; i < D; ++i) Ub[V::M0 + i] = -reb * u[i];
   Ub[V::E] = reb;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) out[v * N + g] = (R)Ub[v];
+  for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = (R)Ub[v];
   }
 }
 
