@@ -12,6 +12,7 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <tuple>
 
 #include "dg.h"
 #include "dg_launch.h"
@@ -82,6 +83,7 @@ struct dg_handle {
   unsigned* stats = nullptr;
   long long splits = 0;          // node splits enqueued since the last reset
   KArgs ka{};
+  KArgs* ka_d = nullptr;         // device copy of ka (read by the persistent kernels)
   // launch geometry
   int epb = 1;                   // elements per block
   int persist = 0;               // persistent blocks per CU (0: one block per item)
@@ -188,7 +190,7 @@ static void lobatto_tables(int k, double* w, double* Dhat) {
 
 static void free_all(dg_handle* h) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
-  F(h->mem_d); F(h->items_d);
+  F(h->mem_d); F(h->items_d); F(h->ka_d);
   for (auto& b : h->bg_d) F(b);
   for (auto& b : h->stage) F(b);
   for (auto& b : h->stage_x) F(b);
@@ -230,6 +232,19 @@ static void build_items(dg_handle* h, int epb) {
       const int c2 = row / md.n[1];
       it.c12 = c1 + (c2 << 16);
       h->items.push_back(it);
+    }
+    if (h->dim == 3) {
+      // Walk y-bands of `by` rows with z outside y inside a band, so the
+      // elements above and below an item were visited at most ~64 items
+      // earlier and are still in the XCD's L2 when their faces are read.
+      const int per_row = (md.n[0] + epb - 1) / epb;
+      const int by = std::max(1, std::min(md.n[1], 64 / std::max(1, per_row)));
+      auto key = [&](const Item& it) {
+        const int c1 = it.c12 & 0xffff, c2 = it.c12 >> 16;
+        return std::make_tuple(c1 / by, c2, c1 % by, it.c0);
+      };
+      std::stable_sort(h->items.begin() + h->item_off[m], h->items.end(),
+                       [&](const Item& x, const Item& y) { return key(x) < key(y); });
     }
   }
   h->item_off.push_back((int)h->items.size());
@@ -276,6 +291,8 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   long long eoff = 0;
   int hoff = 0;
   long long items_max = 0;
+  double wq[kMaxP1], Dq[kMaxP1 * kMaxP1];
+  lobatto_tables(order, wq, Dq);
   for (int m = 0; m < nmembers; ++m) {
     const dg_mesh& g = meshes[m];
     MemberDesc md{};
@@ -286,6 +303,8 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
       md.bc[a] = a < dim ? g.bc[a] : 0;
       const double hh = a < dim ? (g.hi[a] - g.lo[a]) / g.n[a] : 2.0;
       md.two_over_h[a] = 2.0 / hh;
+      md.lift[a][0] = md.two_over_h[a] / wq[0];
+      md.lift[a][1] = md.two_over_h[a] / wq[order];
       if (a < dim) { ne *= g.n[a]; md.J *= 0.5 * hh; }
     }
     for (int a = 0; a < dim; ++a) {
@@ -327,6 +346,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   bool ok = true;
   ok = ok && A((void**)&h->mem_d, sizeof(MemberDesc) * nmembers);
   ok = ok && A((void**)&h->items_d, sizeof(Item) * h->items_cap);
+  ok = ok && A((void**)&h->ka_d, sizeof(KArgs));
   for (auto& b : h->bg_d) ok = ok && A((void**)&b, sizeof(double) * hoff);
   for (auto& b : h->stage) ok = ok && A(&b, h->state_bytes);
   ok = ok && A((void**)&h->auxT, sizeof(double) * h->nnodes);
@@ -386,6 +406,11 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   a.bg_rd = h->bg_d[0]; a.bg_rm = h->bg_d[1]; a.bg_rr = h->bg_d[2]; a.bg_E = h->bg_d[3];
   a.bg_p = h->bg_d[4];
   a.stats = h->stats;
+  if (hipMemcpy(h->ka_d, &h->ka, sizeof(KArgs), hipMemcpyHostToDevice) != hipSuccess) {
+    free_all(h);
+    delete h;
+    return fail(DG_EHIP, "initial upload failed");
+  }
   *out = h;
   return DG_OK;
 }
@@ -475,10 +500,10 @@ static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, cons
   if (mode == 2) h->splits += h->nnodes;
   const LaunchCfg lc = launch_cfg(h);
   if (h->prec == DG_FP64)
-    return Launch<double>::rhs(h->ka, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0,
-                               c1, c2, oT, oS, refresh, s);
-  return Launch<float>::rhs(h->ka, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d, c0, c1,
-                            c2, oT, oS, refresh, s);
+    return Launch<double>::rhs(h->ka, h->ka_d, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0,
+                               h->dt_d, c0, c1, c2, oT, oS, refresh, s);
+  return Launch<float>::rhs(h->ka, h->ka_d, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d,
+                            c0, c1, c2, oT, oS, refresh, s);
 }
 
 extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t s) {
@@ -740,6 +765,7 @@ extern "C" dg_status dg_timing_read(dg_handle* h, int kclass, double* total_ms, 
 static dg_status upload_items(dg_handle* h) {
   HIP_TRY(hipMemcpy(h->items_d, h->items.data(), sizeof(Item) * h->items.size(), hipMemcpyHostToDevice));
   h->ka.nitems = (int)h->items.size();
+  HIP_TRY(hipMemcpy(h->ka_d, &h->ka, sizeof(KArgs), hipMemcpyHostToDevice));
   return DG_OK;
 }
 

@@ -17,6 +17,7 @@ struct MemberDesc {
   double two_over_h[3]; // 2 / h_j
   double J;             // element Jacobian prod_j h_j / 2
   double face_J[3];     // face Jacobian for a face normal to axis j
+  double lift[3][2];    // (2 / h_j) / w_0 and (2 / h_j) / w_K: face-to-node lifting
   long long eoff;       // first global element
   int ne;               // elements of this member
   int hoff;             // first background index (n_z (k+1) entries)

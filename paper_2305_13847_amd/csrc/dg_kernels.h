@@ -10,6 +10,14 @@
 
 namespace dgm {
 
+// The constant address space (read-only global memory; scalar loads) in the
+// device pass.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define DGM_AS_CONST __attribute__((address_space(4)))
+#else
+#define DGM_AS_CONST
+#endif
+
 template <int D>
 struct ElemCoord {
   int c[3];
@@ -169,13 +177,12 @@ __device__ __forceinline__ void gather_nb(const MemberDesc& md, const ElemCoord<
 // fluxes of all directions are staged in LDS behind one barrier.
 template <typename R, int K, int D, int RAIN, int J>
 __device__ __forceinline__ void volume_dir(const MemberDesc& md, int ij, const R* sFJ, R* Rv,
-                                           const R* sD) {
+                                           const R* sD, int t = threadIdx.x) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NV = V::NV;
   constexpr int STR = (J == 0) ? 1 : (J == 1 ? P1 : P1 * P1);
-  const int t = threadIdx.x;
-  const int NT = blockDim.x;
+    constexpr int NT = S::NT;   // LDS row stride (the largest block)
   const R s = (R)md.two_over_h[J];
   const int base = t - ij * STR;
   R d[P1];
@@ -194,7 +201,7 @@ template <typename R, int K, int D, int RAIN, int J>
 __device__ __forceinline__ void stage_flux(const Pt<R, D, RAIN>& q, R* sFJ) {
   using V = Vars<D, RAIN>;
   constexpr int NV = V::NV;
-  const int NT = blockDim.x;
+  constexpr int NT = Shape<K, D>::NT;   // LDS row stride (the largest block)
   R F[NV];
   flux<R, D, RAIN, J>(q, F);
 #pragma unroll
@@ -231,14 +238,357 @@ __device__ __forceinline__ void face_dir(const KArgs& a, const MemberDesc& md, i
   const R Lam = plus ? ((lo >= ln) ? lo : ln) : ((ln >= lo) ? ln : lo);
   const R half = R(0.5);
   if (plus) {
-    const R lift = (R)(md.two_over_h[J] / a.w[K]);
+    const R lift = (R)md.lift[J][1];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Rv[v] -= lift * (half * (F[v] + Fn[v]) + half * Lam * (Uq[v] - Un[v]));
   } else {
-    const R lift = (R)(md.two_over_h[J] / a.w[0]);
+    const R lift = (R)md.lift[J][0];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Rv[v] += lift * (half * (Fn[v] + F[v]) + half * Lam * (Un[v] - Uq[v]));
   }
+}
+
+// Face work of a block as (element, direction J, side, face node) pairs, PE =
+// 2 (K+1)^(D-1) per element and direction.  The pairs of one direction are cut
+// into slot-waves of WL = min(64, NT) lanes; full wavefronts take the
+// slot-waves in turn, so every lane of a pass holds one face node (a
+// node-per-thread face loop leaves the lanes of interior nodes idle in each
+// of the D directions) and J is uniform across a wavefront.
+template <int K, int D>
+struct FaceShape {
+  static constexpr int P1 = K + 1;
+  static constexpr int FN = (D == 2) ? P1 : P1 * P1;  // nodes per face
+  static constexpr int NP = Shape<K, D>::NP;
+  // face passes whose neighbour traces are gathered before the volume term:
+  // in FP32 none (the registers held across it would cost a wave per SIMD),
+  // in FP64 two (occupancy is set by the FP64 registers anyway)
+  template <typename R>
+  static constexpr int kpre() { return sizeof(R) == 4 ? 0 : 2; }
+};
+
+struct SlotPlan {
+  int wl, pj, swj, sw, nfull, wave, lane;
+  __device__ __forceinline__ SlotPlan(int NT, int NP, int FN, int dim, int t) {
+    wl = NT < 64 ? NT : 64;
+    pj = (NT / NP) * 2 * FN;
+    swj = (pj + wl - 1) / wl;
+    sw = dim * swj;
+    nfull = NT / wl;
+    wave = t / wl;
+    lane = t - wave * wl;
+  }
+  // slot-wave of pass k for this thread's wavefront, or -1
+  __device__ __forceinline__ int slot_wave(int k) const {
+    if (wave >= nfull) return -1;
+    const int s = wave + k * nfull;
+    return s < sw ? __builtin_amdgcn_readfirstlane(s) : -1;
+  }
+};
+
+template <typename R, int D, int RAIN>
+struct Pair {
+  Nb<R, D, RAIN> nb;
+  int slot;   // block slot (le * NP + n) of the own node; -1: nothing to do
+  int side, izn;
+};
+
+// Pair q of direction J: decode the own node and gather the neighbour's trace.
+// Inactive elements and wall faces get slot = -1 (the node's own thread handles
+// walls: the ghost is its own reflected point state).
+template <typename R, int K, int D, int RAIN, int J>
+__device__ __forceinline__ void pair_gather(const MemberDesc& md, const Item& item, int q, int pj,
+                                            const R* __restrict__ U, const double* __restrict__ auxT,
+                                            const double* __restrict__ auxS, unsigned N,
+                                            Pair<R, D, RAIN>& pr) {
+  using FS = FaceShape<K, D>;
+  using V = Vars<D, RAIN>;
+  constexpr int P1 = FS::P1, FN = FS::FN, NP = FS::NP, NV = V::NV;
+  constexpr int STR = (J == 0) ? 1 : (J == 1 ? P1 : P1 * P1);
+  pr.slot = -1;
+  pr.side = 0;
+  pr.izn = 0;
+  if (q >= pj) return;
+  const int le = q / (2 * FN);
+  const int r = q - le * (2 * FN);
+  const int side = r / FN;
+  const int f = r - side * FN;
+  const int e = item.e0 + le;
+  if (e >= md.ne) return;
+  // own node: index K*side along J, the face node f over the other axes
+  const int fa = f % P1, fb = f / P1;
+  int n;
+  if (J == 0) n = side * K + P1 * fa + P1 * P1 * fb;
+  else if (J == 1) n = fa + P1 * side * K + P1 * P1 * fb;
+  else n = fa + P1 * fb + P1 * P1 * side * K;
+  const ElemCoord<D> ec = item_coord<D>(md, item, le);
+  const int c = ec.c[J];
+  const bool at_end = side ? (c == md.n[J] - 1) : (c == 0);
+  if (at_end && md.bc[J] == 1) return;
+  int cn = side ? c + 1 : c - 1;
+  if (cn < 0) cn += md.n[J];
+  if (cn >= md.n[J]) cn -= md.n[J];
+  const int en = e + (cn - c) * elem_stride(md, J);
+  const int nn = side ? n - K * STR : n + K * STR;
+  const unsigned gn = (unsigned)(md.eoff + en) * NP + nn;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) pr.nb.U[v] = (U + (size_t)v * N)[gn];
+  pr.nb.T = auxT[gn];
+  pr.nb.rvs = auxS[gn];
+  const int lz = (D == 2) ? (J == 0 ? fa : side * K) : (J == 2 ? side * K : fb);
+  pr.izn = md.hoff + ((J == D - 1) ? cn * P1 + (side ? 0 : K) : ec.c[D - 1] * P1 + lz);
+  pr.slot = le * NP + n;
+  pr.side = side;
+}
+
+template <typename R, int K, int D, int RAIN>
+__device__ __forceinline__ void pair_gather_rt(int J, const MemberDesc& md, const Item& item, int q, int pj,
+                                               const R* __restrict__ U, const double* __restrict__ auxT,
+                                               const double* __restrict__ auxS, unsigned N,
+                                               Pair<R, D, RAIN>& pr) {
+  if (J == 0) pair_gather<R, K, D, RAIN, 0>(md, item, q, pj, U, auxT, auxS, N, pr);
+  else if (D == 2 || J == 1) pair_gather<R, K, D, RAIN, 1>(md, item, q, pj, U, auxT, auxS, N, pr);
+  else pair_gather<R, K, D, RAIN, (D == 3 ? 2 : 1)>(md, item, q, pj, U, auxT, auxS, N, pr);
+}
+
+// Lax-Friedrichs flux of one pair (Section 3.2): the own trace (U, F_J,
+// lambda_J) comes from the block's LDS tiles, the neighbour's is evaluated
+// here.  The lifted correction replaces F_J at the own slot of sF:
+// +-(lift/2)(F + F_n) + (lift/2) Lambda (U_n - U), + on the minus face.
+template <typename R, int K, int D, int RAIN, int J>
+__device__ __forceinline__ void pair_flux(const KArgs& a, const MemberDesc& md, const Pair<R, D, RAIN>& pr,
+                                          R* sF, const R* sU, const R* sL) {
+  using V = Vars<D, RAIN>;
+  constexpr int NV = V::NV;
+  constexpr int NT = Shape<K, D>::NT;
+  if (pr.slot < 0) return;
+  Pt<R, D, RAIN> qn;
+  eval_point<R, D, RAIN>(a, pr.nb.U, pr.nb.T, pr.nb.rvs, pr.izn, qn);
+  R Fn[NV];
+  flux<R, D, RAIN, J>(qn, Fn);
+  const R ln = wave_speed<R, D, RAIN, J>(qn);
+  R* F = sF + J * (NV * NT) + pr.slot;
+  const R* Uo = sU + pr.slot;
+  const R lo = sL[J * NT + pr.slot];
+  // Lambda = max over the two sides, ties to the minus side
+  const bool own = pr.side ? (lo >= ln) : !(ln >= lo);
+  const R Lam = own ? lo : ln;
+  const R hl = R(0.5) * (pr.side ? (R)md.lift[J][1] : (R)md.lift[J][0]);
+  const R kf = pr.side ? -hl : hl;
+  const R kj = hl * Lam;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) F[v * NT] = kf * (F[v * NT] + Fn[v]) + kj * (pr.nb.U[v] - Uo[v * NT]);
+}
+
+template <typename R, int K, int D, int RAIN>
+__device__ __forceinline__ void pair_flux_rt(int J, const KArgs& a, const MemberDesc& md,
+                                             const Pair<R, D, RAIN>& pr, R* sF, const R* sU, const R* sL) {
+  if (J == 0) pair_flux<R, K, D, RAIN, 0>(a, md, pr, sF, sU, sL);
+  else if (D == 2 || J == 1) pair_flux<R, K, D, RAIN, 1>(a, md, pr, sF, sU, sL);
+  else pair_flux<R, K, D, RAIN, (D == 3 ? 2 : 1)>(a, md, pr, sF, sU, sL);
+}
+
+// Stage update and the split epilogue shared by both face schemes.
+template <typename R, int D, int RAIN, int MODE>
+__device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg, unsigned g, unsigned N,
+                                               const R* Uq, const R* U0q, const R* Rv, double T, double rvs,
+                                               R* __restrict__ out, double dtm, double c0, double c1,
+                                               double c2, double* __restrict__ oT,
+                                               double* __restrict__ oS, int refresh, int& iters, int& bad) {
+  using V = Vars<D, RAIN>;
+  constexpr int NV = V::NV;
+  if (MODE == 0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = Rv[v];
+    return;
+  }
+  const R k2 = (R)(c2 * dtm);
+  const R k1 = (R)c1;
+  R Un[NV];
+  if (c0 != 0.0) {
+    const R k0 = (R)c0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = k0 * U0q[v] + k1 * Uq[v] + k2 * Rv[v];
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = k1 * Uq[v] + k2 * Rv[v];
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = Un[v];
+  if (MODE == 2) {
+    // split of the new state (FP64), warm-started at this node's (T, rho_vs);
+    // bg = (rho_d, rho_m, rho_r, E) of the background at this node
+    const double rd = bg[0] + (double)Un[V::RD];
+    const double rm = bg[1] + (double)Un[V::RM];
+    const double rr = RAIN ? bg[2] + (double)Un[V::RR] : 0.0;
+    double ke = 0.0;
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      const double mi = (double)Un[V::M0 + i];
+      ke += mi * mi;
+    }
+    const double re = bg[3] + (double)Un[V::E] - 0.5 * ke * rcp64(rd + rm + rr);
+    Anchor A;
+    A.T0 = 0.0; A.r0 = 0.0; A.inv0 = 0.0;
+    if (T > 150.0 && T < 600.0 && rvs > 0.0) {
+      A.T0 = T; A.r0 = rvs; A.inv0 = rcp64(T);
+    }
+    // the branch that held at this node before is tried first
+    const SplitOut s = split_point_anchor(a, rd, rm, rr, re, T, A, rvs < rm);
+    iters = s.iters;
+    bad = s.bad;
+    oT[g] = s.T;
+    oS[g] = (refresh && s.bad == 0) ? rho_vs(a, s.T) : s.rvs;
+  }
+}
+
+// Right-hand side / stage of one work item with the lane-dense face pass
+// (K >= 2, where a node lies on at most one face per direction).  LDS tiles
+// use the compile-time stride NT of the largest block; smaller blocks use a
+// prefix of each row.
+template <typename R, int K, int D, int RAIN, int MODE, int KPRE>
+__device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R* sF, R* sU, R* sL,
+                                               const R* sD, const R* __restrict__ U,
+                                               const double* __restrict__ auxT,
+                                               const double* __restrict__ auxS, R* __restrict__ out,
+                                               const R* __restrict__ U0, const double* __restrict__ dt_m,
+                                               double c0, double c1, double c2, double* __restrict__ oT,
+                                               double* __restrict__ oS, int refresh) {
+  using S = Shape<K, D>;
+  using V = Vars<D, RAIN>;
+  using FS = FaceShape<K, D>;
+  constexpr int P1 = S::P1, NP = S::NP, NV = V::NV, NT = S::NT;
+  static_assert(K >= 2, "pair face pass needs K >= 2");
+  const Item item = a.items[it_];
+  const MemberDesc& md = a.mem[item.member];
+  const int le = t / NP, n = t - le * NP;
+  const int e = item.e0 + le;
+  const bool active = e < md.ne;
+  const unsigned N = a.nnodes;
+  const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
+  const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
+  int idx[3];
+  idx[0] = n % P1;
+  idx[1] = (n / P1) % P1;
+  idx[2] = (D == 3) ? n / (P1 * P1) : 0;
+  const int iz = md.hoff + ec.c[D - 1] * P1 + idx[D - 1];
+  R Uq[NV];
+  double T = 300.0, rvs = 0.0;
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Uq[v] = (U + (size_t)v * N)[g];
+    T = auxT[g];
+    rvs = auxS[g];
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Uq[v] = R(0);
+  }
+  // neighbour traces of the first passes: issued before any arithmetic
+  const SlotPlan sp((int)blockDim.x, NP, FS::FN, D, t);
+  Pair<R, D, RAIN> pr[KPRE > 0 ? KPRE : 1];
+  int pj_[KPRE > 0 ? KPRE : 1];
+#pragma unroll
+  for (int k = 0; k < KPRE; ++k) {
+    const int s = sp.slot_wave(k);
+    pr[k].slot = -1;
+    pj_[k] = -1;
+    if (s >= 0) {
+      const int J = s / sp.swj;
+      pj_[k] = J;
+      pair_gather_rt<R, K, D, RAIN>(J, md, item, (s - J * sp.swj) * sp.wl + sp.lane, sp.pj, U, auxT, auxS,
+                                    N, pr[k]);
+    }
+  }
+
+  Pt<R, D, RAIN> q;
+  eval_point<R, D, RAIN>(a, Uq, T, rvs, active ? iz : md.hoff, q);
+  {
+    R F[NV];
+    flux<R, D, RAIN, 0>(q, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sF[v * NT + t] = F[v];
+    flux<R, D, RAIN, 1>(q, F);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sF[(NV + v) * NT + t] = F[v];
+    if constexpr (D == 3) {
+      flux<R, D, RAIN, 2>(q, F);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sF[(2 * NV + v) * NT + t] = F[v];
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < NV; ++v) sU[v * NT + t] = Uq[v];
+  sL[t] = wave_speed<R, D, RAIN, 0>(q);
+  sL[NT + t] = wave_speed<R, D, RAIN, 1>(q);
+  if constexpr (D == 3) sL[2 * NT + t] = wave_speed<R, D, RAIN, 2>(q);
+  __syncthreads();
+  R U0q[NV];
+  double bg[4] = {0.0, 0.0, 0.0, 0.0};
+  const double dtm = (MODE != 0) ? dt_m[item.member] : 0.0;
+  R Rv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Rv[v] = R(0);
+  bool fa[3], wl[3];
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    fa[j] = j < D && active && (idx[j] == 0 || idx[j] == K);
+    const bool at_end = (idx[j] == K) ? (ec.c[j] == md.n[j] - 1) : (ec.c[j] == 0);
+    wl[j] = fa[j] && at_end && md.bc[j] == 1;
+  }
+  if (active) {
+    volume_dir<R, K, D, RAIN, 0>(md, idx[0], sF, Rv, sD, t);
+    volume_dir<R, K, D, RAIN, 1>(md, idx[1], sF + NV * NT, Rv, sD, t);
+    if constexpr (D == 3) volume_dir<R, K, D, RAIN, 2>(md, idx[2], sF + 2 * NV * NT, Rv, sD, t);
+    // slip walls: the ghost is this node's own reflected state
+    Nb<R, D, RAIN> none;
+    if (wl[0]) face_dir<R, K, D, RAIN, 0>(a, md, idx[0], iz, Uq, q, none, true, -1, Rv);
+    if (wl[1]) face_dir<R, K, D, RAIN, 1>(a, md, idx[1], iz, Uq, q, none, true, -1, Rv);
+    if constexpr (D == 3) {
+      if (wl[2]) face_dir<R, K, D, RAIN, 2>(a, md, idx[2], iz, Uq, q, none, true, -1, Rv);
+    }
+    sources<R, D, RAIN>(a, Uq, q, Rv);
+  }
+  __syncthreads();   // the volume term has read sF
+#pragma unroll
+  for (int k = 0; k < KPRE; ++k)
+    if (pj_[k] >= 0) pair_flux_rt<R, K, D, RAIN>(pj_[k], a, md, pr[k], sF, sU, sL);
+#pragma clang loop unroll(disable)
+  for (int k = KPRE;; ++k) {
+    const int s = sp.slot_wave(k);
+    if (s < 0) break;
+    const int J = s / sp.swj;
+    Pair<R, D, RAIN> p1;
+    pair_gather_rt<R, K, D, RAIN>(J, md, item, (s - J * sp.swj) * sp.wl + sp.lane, sp.pj, U, auxT, auxS, N,
+                                  p1);
+    pair_flux_rt<R, K, D, RAIN>(J, a, md, p1, sF, sU, sL);
+  }
+  // operands of the stage update and the split, fetched while the faces of
+  // the other wavefronts finish
+  if (MODE != 0 && active && c0 != 0.0) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) U0q[v] = (U0 + (size_t)v * N)[g];
+  }
+  if (MODE == 2 && active) {
+    bg[0] = a.bg_rd[iz];
+    bg[1] = a.bg_rm[iz];
+    if (RAIN) bg[2] = a.bg_rr[iz];
+    bg[3] = a.bg_E[iz];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (fa[j] && !wl[j]) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Rv[v] += sF[(j * NV + v) * NT + t];
+    }
+  int iters = 0, bad = 0;
+  if (active) {
+    R Us[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Us[v] = sU[v * NT + t];
+    stage_epilogue<R, D, RAIN, MODE>(a, bg, g, N, Us, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS, refresh,
+                                     iters, bad);
+  }
+  if (MODE == 2) record_stats(a, iters, bad);
 }
 
 template <typename R, int K, int D, int RAIN, int MODE>
@@ -358,8 +708,14 @@ __device__ __forceinline__ void rhs_item(const KArgs& a, int it_, R (*sF)[Vars<D
 }
 
 // one work item per block
+// FP32: at least 4 wavefronts per SIMD (the register budget the kernel fits
+// without spills); FP64 kernels need more registers than that and are left to
+// the compiler (spills cost far more than the occupancy they buy).
+template <typename R>
+constexpr int min_waves() { return sizeof(R) == 4 ? 4 : 1; }
+
 template <typename R, int K, int D, int RAIN, int MODE>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<R>())))
 rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
            const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
            const double* __restrict__ dt_m, double c0, double c1, double c2,
@@ -367,34 +723,61 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1;
+  constexpr bool PAIRS = K >= 2;
   __shared__ R sF[D][V::NV * S::NT];
   __shared__ R sD[P1 * P1];
+  __shared__ R sU[PAIRS ? V::NV * S::NT : 1];
+  __shared__ R sL[PAIRS ? D * S::NT : 1];
   if (threadIdx.x < P1 * P1) sD[threadIdx.x] = (R)a.Dhat[threadIdx.x];
   const ItemWalk walk(a.nitems);
   const int it_ = walk.item(0);
   if (it_ < 0) return;
-  rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
+  if constexpr (PAIRS)
+    rhs_item_pairs<R, K, D, RAIN, MODE, FaceShape<K, D>::template kpre<R>()>(
+        a, threadIdx.x, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
+  else
+    rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
 }
 
 // persistent: a grid smaller than the item count walks the items
 template <typename R, int K, int D, int RAIN, int MODE>
-__global__ void __launch_bounds__(256)
-rhs_kernel_persistent(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<R>())))
+rhs_kernel_persistent(KArgs a, const KArgs* __restrict__ a_dev, const R* __restrict__ U,
+                      const double* __restrict__ auxT,
                       const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
                       const double* __restrict__ dt_m, double c0, double c1, double c2,
                       double* __restrict__ oT, double* __restrict__ oS, int refresh) {
   using S = Shape<K, D>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1;
+  constexpr bool PAIRS = K >= 2;
   __shared__ R sF[D][V::NV * S::NT];
   __shared__ R sD[P1 * P1];
+  __shared__ R sU[PAIRS ? V::NV * S::NT : 1];
+  __shared__ R sL[PAIRS ? D * S::NT : 1];
   if (threadIdx.x < P1 * P1) sD[threadIdx.x] = (R)a.Dhat[threadIdx.x];
   const ItemWalk walk(a.nitems);
+#pragma clang loop unroll(disable)
   for (int kk = 0;; ++kk) {
     const int it_ = walk.item(kk);
     if (it_ < 0) break;
-    rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
-    __syncthreads();   // sF is reused by the next item
+    // The argument block (its device copy a_dev) and the thread index pass
+    // through opaque copies in every iteration: constants and per-thread
+    // values hoisted out of the loop would stay live across it and exhaust
+    // the registers.  No face pass is gathered ahead.
+    unsigned long long apv = (unsigned long long)a_dev;
+    asm volatile("" : "+s"(apv));
+    // constant address space: the block is read-only during the launch, so
+    // its fields are scalar loads
+    const KArgs DGM_AS_CONST* ap = (const KArgs DGM_AS_CONST*)apv;
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    if constexpr (PAIRS)
+      rhs_item_pairs<R, K, D, RAIN, MODE, 0>(*ap, t, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m,
+                                             c0, c1, c2, oT, oS, refresh);
+    else
+      rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
+    __syncthreads();   // the LDS tiles are reused by the next item
   }
 }
 

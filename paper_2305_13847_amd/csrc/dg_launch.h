@@ -61,7 +61,7 @@ struct Launch {
 
   // mode 0: out = dU/dt; mode 1: out = c0 U0 + c1 U + c2 dt dU/dt; mode 2: mode 1 and the split
   // of out into (oT, oS)
-  static bool rhs(const KArgs& a, LaunchCfg lc, int K, int D, int rain, int mode, const void* U,
+  static bool rhs(const KArgs& a, const KArgs* a_dev, LaunchCfg lc, int K, int D, int rain, int mode, const void* U,
                   const double* auxT, const double* auxS, void* out, const void* U0,
                   const double* dt, double c0, double c1, double c2, double* oT, double* oS,
                   int refresh, hipStream_t s) {
@@ -76,7 +76,9 @@ struct Launch {
       if (mode == 0) DGM_RHS(rhs_kernel, 0);
       else if (mode == 1) DGM_RHS(rhs_kernel, 1);
       else if (!persist) DGM_RHS(rhs_kernel, 2);
-      else DGM_RHS(rhs_kernel_persistent, 2);
+      else
+        hipLaunchKernelGGL((rhs_kernel_persistent<R, K_, D_, R_, 2>), grid, block, 0, s, a, a_dev, (const R*)U,
+                           auxT, auxS, (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, refresh);
 #undef DGM_RHS
     });
   }
