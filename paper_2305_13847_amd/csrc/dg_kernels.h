@@ -259,11 +259,6 @@ struct FaceShape {
   static constexpr int P1 = K + 1;
   static constexpr int FN = (D == 2) ? P1 : P1 * P1;  // nodes per face
   static constexpr int NP = Shape<K, D>::NP;
-  // face passes whose neighbour traces are gathered before the volume term:
-  // in FP32 none (the registers held across it would cost a wave per SIMD),
-  // in FP64 two (occupancy is set by the FP64 registers anyway)
-  template <typename R>
-  static constexpr int kpre() { return sizeof(R) == 4 ? 0 : 2; }
 };
 
 struct SlotPlan {
@@ -376,7 +371,7 @@ __device__ __forceinline__ void pair_flux(const KArgs& a, const MemberDesc& md, 
   const R kf = pr.side ? -hl : hl;
   const R kj = hl * Lam;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) F[v * NT] = kf * (F[v * NT] + Fn[v]) + kj * (pr.nb.U[v] - Uo[v * NT]);
+  for (int v = 0; v < NV; ++v) F[v * NT] = fma(kf, F[v * NT] + Fn[v], kj * (pr.nb.U[v] - Uo[v * NT]));
 }
 
 template <typename R, int K, int D, int RAIN>
@@ -445,7 +440,7 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
 // (K >= 2, where a node lies on at most one face per direction).  LDS tiles
 // use the compile-time stride NT of the largest block; smaller blocks use a
 // prefix of each row.
-template <typename R, int K, int D, int RAIN, int MODE, int KPRE>
+template <typename R, int K, int D, int RAIN, int MODE>
 __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R* sF, R* sU, R* sL,
                                                const R* sD, const R* __restrict__ U,
                                                const double* __restrict__ auxT,
@@ -482,22 +477,7 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
 #pragma unroll
     for (int v = 0; v < NV; ++v) Uq[v] = R(0);
   }
-  // neighbour traces of the first passes: issued before any arithmetic
   const SlotPlan sp((int)blockDim.x, NP, FS::FN, D, t);
-  Pair<R, D, RAIN> pr[KPRE > 0 ? KPRE : 1];
-  int pj_[KPRE > 0 ? KPRE : 1];
-#pragma unroll
-  for (int k = 0; k < KPRE; ++k) {
-    const int s = sp.slot_wave(k);
-    pr[k].slot = -1;
-    pj_[k] = -1;
-    if (s >= 0) {
-      const int J = s / sp.swj;
-      pj_[k] = J;
-      pair_gather_rt<R, K, D, RAIN>(J, md, item, (s - J * sp.swj) * sp.wl + sp.lane, sp.pj, U, auxT, auxS,
-                                    N, pr[k]);
-    }
-  }
 
   Pt<R, D, RAIN> q;
   eval_point<R, D, RAIN>(a, Uq, T, rvs, active ? iz : md.hoff, q);
@@ -548,11 +528,12 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
     sources<R, D, RAIN>(a, Uq, q, Rv);
   }
   __syncthreads();   // the volume term has read sF
-#pragma unroll
-  for (int k = 0; k < KPRE; ++k)
-    if (pj_[k] >= 0) pair_flux_rt<R, K, D, RAIN>(pj_[k], a, md, pr[k], sF, sU, sL);
+  // face passes: the neighbour traces are gathered here, not ahead of the
+  // volume term (registers held across it would cost a wavefront per SIMD),
+  // and every pass runs the same code, so the rounding of a face flux does
+  // not depend on the pass (the launch geometry) that computes it
 #pragma clang loop unroll(disable)
-  for (int k = KPRE;; ++k) {
+  for (int k = 0;; ++k) {
     const int s = sp.slot_wave(k);
     if (s < 0) break;
     const int J = s / sp.swj;
@@ -733,7 +714,7 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   const int it_ = walk.item(0);
   if (it_ < 0) return;
   if constexpr (PAIRS)
-    rhs_item_pairs<R, K, D, RAIN, MODE, FaceShape<K, D>::template kpre<R>()>(
+    rhs_item_pairs<R, K, D, RAIN, MODE>(
         a, threadIdx.x, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
   else
     rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
@@ -764,7 +745,7 @@ rhs_kernel_persistent(KArgs a, const KArgs* __restrict__ a_dev, const R* __restr
     // The argument block (its device copy a_dev) and the thread index pass
     // through opaque copies in every iteration: constants and per-thread
     // values hoisted out of the loop would stay live across it and exhaust
-    // the registers.  No face pass is gathered ahead.
+    // the registers.
     unsigned long long apv = (unsigned long long)a_dev;
     asm volatile("" : "+s"(apv));
     // constant address space: the block is read-only during the launch, so
@@ -773,7 +754,7 @@ rhs_kernel_persistent(KArgs a, const KArgs* __restrict__ a_dev, const R* __restr
     int t = threadIdx.x;
     asm volatile("" : "+v"(t));
     if constexpr (PAIRS)
-      rhs_item_pairs<R, K, D, RAIN, MODE, 0>(*ap, t, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m,
+      rhs_item_pairs<R, K, D, RAIN, MODE>(*ap, t, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m,
                                              c0, c1, c2, oT, oS, refresh);
     else
       rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
