@@ -140,8 +140,12 @@ class Oracle:
         return cls(case.mesh, P, case.nvars, case.bg)
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().ora_destroy(self.h)
+        # at interpreter exit the module globals may already be gone
+        if getattr(self, "h", None) and lib is not None:
+            try:
+                lib().ora_destroy(self.h)
+            except Exception:
+                pass
             self.h = None
 
     def pbar(self) -> np.ndarray:
