@@ -1,0 +1,107 @@
+"""The C ABI as seen from the host, without a GPU.
+
+* every function declared in include/dg.h is exported by the built library,
+  and the Python binding lists exactly those functions;
+* the ctypes mirrors of dg_mesh, dg_params and dg_stats have the header's
+  size and field offsets (a C probe compiled against the header prints them);
+* dg_default_params fills in the constants of the paper's table, the same
+  numbers the reference implementation uses;
+* on a host with no GPU, creating a handle fails with an error status and a
+  message instead of falling back to anything.
+"""
+import ctypes as ct
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+import oracle as O
+from paper_2305_13847_amd import lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dg.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(dg_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_header_declares_the_documented_calls():
+    names = _declared()
+    for core in ("dg_create", "dg_rhs", "dg_saturation_split", "dg_rk_step", "dg_rhs_vjp"):
+        assert core in names
+    assert len(names) >= 20
+
+
+def test_every_declared_function_is_exported():
+    L = lib.load()
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_exactly_the_header():
+    assert sorted(lib.EXPORTS) == _declared()
+
+
+PROBE = r"""
+#include <stddef.h>
+#include <stdio.h>
+#include "dg.h"
+#define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("dg_mesh %zu\ndg_params %zu\ndg_stats %zu\n", sizeof(dg_mesh), sizeof(dg_params), sizeof(dg_stats));
+  F(dg_mesh, dim) F(dg_mesh, n) F(dg_mesh, lo) F(dg_mesh, hi) F(dg_mesh, bc)
+  F(dg_params, g) F(dg_params, pref) F(dg_params, rain) F(dg_params, vr_mode) F(dg_params, vr_const)
+  F(dg_params, q_au) F(dg_params, precision) F(dg_params, rk) F(dg_params, newton_rtol)
+  F(dg_params, newton_maxit)
+  F(dg_stats, splits) F(dg_stats, nonconverged) F(dg_stats, max_iters) F(dg_stats, nonfinite)
+  return 0;
+}
+"""
+
+
+def test_struct_layouts_match_the_header():
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "probe.cpp"), os.path.join(d, "probe")
+        open(src, "w").write(PROBE)
+        cmd = ["g++", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"), "-I", "/opt/rocm/include",
+               src, "-o", exe]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            pytest.skip("cannot compile the header probe: " + r.stderr[-300:])
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
+    structs = {"dg_mesh": lib.dg_mesh, "dg_params": lib.dg_params, "dg_stats": lib.dg_stats}
+    for key, val in got.items():
+        if "." in key:
+            s, f = key.split(".")
+            assert getattr(structs[s], f).offset == int(val), key
+        else:
+            assert ct.sizeof(structs[key]) == int(val), key
+
+
+def test_default_params_are_the_paper_constants():
+    L = lib.load()
+    p = lib.dg_params()
+    L.dg_default_params(ct.byref(p))
+    ref = O.default_params()
+    for name, _ in lib.dg_params._fields_:
+        if hasattr(ref, name) and name not in ("precision", "rk"):
+            assert getattr(p, name) == getattr(ref, name), name
+    assert p.precision == lib.DG_FP64 and p.rk == lib.DG_SSPRK43
+
+
+def test_create_without_a_device_fails_loudly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2305_13847_amd import synth
+    c = synth.periodic_smooth(n=(4, 4), order=2, seed=1)
+    with pytest.raises(lib.DGError) as e:
+        lib.for_case(c, precision=lib.DG_FP64)
+    assert "dg status" in str(e.value)
