@@ -105,7 +105,9 @@ typedef struct {
 void dg_default_params(dg_params* p);
 
 /* Create a handle for one mesh.  order k in 1..4, nvars = 3 + dim (rain = 0)
- * or 4 + dim (rain = 1), otherwise DG_EINVAL.  *out receives the handle. */
+ * or 4 + dim (rain = 1), otherwise DG_EINVAL.  A handle holds fewer than
+ * 2^29 nodes in FP64 and 2^30 in FP32 bulk (each variable's array stays below
+ * 4 GiB), otherwise DG_EINVAL.  *out receives the handle. */
 dg_status dg_create(const dg_mesh* mesh, int order, int nvars, const dg_params* p,
                     dg_handle** out);
 

@@ -334,9 +334,10 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   h->bg_set.assign(nmembers, 0);
   h->etot = eoff;
   h->nnodes = eoff * h->np;
-  if (h->nnodes >= (1LL << 31)) {
+  // per-variable arrays are addressed with 32-bit byte offsets
+  if (h->nnodes >= (p->precision == DG_FP64 ? (1LL << 29) : (1LL << 30))) {
     delete h;
-    return fail(DG_EINVAL, "a handle holds at most 2^31 - 1 nodes");
+    return fail(DG_EINVAL, "a handle holds fewer than 2^29 (FP64) or 2^30 (FP32 bulk) nodes");
   }
   const size_t rsz = h->prec == DG_FP64 ? sizeof(double) : sizeof(float);
   h->state_bytes = (size_t)nvars * h->nnodes * rsz;

@@ -27,6 +27,45 @@ struct Shape {
 };
 
 // ---------------------------------------------------------------------------
+// per-variable device arrays through buffer resources
+// ---------------------------------------------------------------------------
+// One 128-bit descriptor (base address, byte size, raw 32-bit data format)
+// per array, built with scalar instructions; accesses take a 32-bit byte
+// offset, so no 64-bit address arithmetic per load, and the hardware drops
+// accesses past the end (reads return 0).  Array byte sizes stay below 4 GiB
+// (the handle limits its node count accordingly).
+constexpr int kRawBufferWord3 = 0x00020000;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const T* base, unsigned n) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(n * (unsigned)sizeof(T)), kRawBufferWord3);
+}
+
+__device__ __forceinline__ float buf_load(__amdgpu_buffer_rsrc_t r, unsigned i, float*) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4u, 0, 0));
+}
+__device__ __forceinline__ double buf_load(__amdgpu_buffer_rsrc_t r, unsigned i, double*) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8u, 0, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned i, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, i * 4u, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, unsigned i, double v) {
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, i * 8u, 0, 0);
+}
+
+// element i of variable v of an SoA state (v-major, n nodes per variable)
+template <typename T>
+__device__ __forceinline__ T ld(const T* base, unsigned n, int v, unsigned i) {
+  return buf_load(buf_rsrc(base + (size_t)v * n, n), i, (T*)nullptr);
+}
+template <typename T>
+__device__ __forceinline__ void st(T* base, unsigned n, int v, unsigned i, T x) {
+  buf_store(buf_rsrc(base + (size_t)v * n, n), i, x);
+}
+
+// ---------------------------------------------------------------------------
 // saturation vapour density and the split (FP64)
 // ---------------------------------------------------------------------------
 // rho_vs(T) = e_s(T) / (R_v T) with the Clausius-Clapeyron e_s of Section 2.1,
@@ -66,14 +105,30 @@ __device__ __forceinline__ bool in_anchor(const Anchor& A, double T) {
   return fabs(T - A.T0) <= kAnchorX * A.T0;
 }
 
+// Between two stages T moves by far less than the anchor range, and for
+// |x| <= kShortX shorter series suffice (anchors lie above 150 K, so
+// b / T0 < 46): log(1 + x) to x^4 (error |x|^5/5 < 3e-21), 1/(1 + x) to x^3
+// (error x^4 = 1e-16, entering d multiplied by b x / T0 < 5e-3) and
+// exp(d) - 1 to d^5 (|d| < 5.2e-3, error d^6/720 < 3e-17).  The choice is
+// made per wavefront.
+constexpr double kShortX = 1.0e-4;
+
 // rho_vs(T) and d rho_vs / dT from the anchor
 __device__ __forceinline__ double rvs_near(const KArgs& a, const Anchor& A, double T, double* drvs) {
   const double x = (T - A.T0) * A.inv0;
-  const double l = x * (1.0 + x * (-0.5 + x * (1.0 / 3.0 + x * (-0.25 + x * (0.2 + x * (-1.0 / 6.0 + x * (1.0 / 7.0)))))));
-  const double q = 1.0 + x * (-1.0 + x * (1.0 + x * (-1.0 + x * (1.0 + x * (-1.0 + x * (1.0 - x))))));
-  const double d = a.am1 * l + a.b * A.inv0 * x * q;
-  const double e = d * (1.0 + d * (1.0 / 2 + d * (1.0 / 6 + d * (1.0 / 24 + d * (1.0 / 120 + d * (1.0 / 720 +
-                   d * (1.0 / 5040 + d * (1.0 / 40320 + d * (1.0 / 362880 + d * (1.0 / 3628800))))))))));
+  double l, q, e;
+  if (__all(fabs(x) <= kShortX)) {
+    l = x * (1.0 + x * (-0.5 + x * (1.0 / 3.0 - x * 0.25)));
+    q = 1.0 + x * (-1.0 + x * (1.0 - x));
+    const double d = a.am1 * l + a.b * A.inv0 * x * q;
+    e = d * (1.0 + d * (1.0 / 2 + d * (1.0 / 6 + d * (1.0 / 24 + d * (1.0 / 120)))));
+  } else {
+    l = x * (1.0 + x * (-0.5 + x * (1.0 / 3.0 + x * (-0.25 + x * (0.2 + x * (-1.0 / 6.0 + x * (1.0 / 7.0)))))));
+    q = 1.0 + x * (-1.0 + x * (1.0 + x * (-1.0 + x * (1.0 + x * (-1.0 + x * (1.0 - x))))));
+    const double d = a.am1 * l + a.b * A.inv0 * x * q;
+    e = d * (1.0 + d * (1.0 / 2 + d * (1.0 / 6 + d * (1.0 / 24 + d * (1.0 / 120 + d * (1.0 / 720 +
+        d * (1.0 / 5040 + d * (1.0 / 40320 + d * (1.0 / 362880 + d * (1.0 / 3628800))))))))));
+  }
   const double r = A.r0 + A.r0 * e;
   const double invT = A.inv0 * q;
   *drvs = r * (a.am1 + a.b * invT) * invT;

@@ -326,9 +326,9 @@ __device__ __forceinline__ void pair_gather(const MemberDesc& md, const Item& it
   const int nn = side ? n - K * STR : n + K * STR;
   const unsigned gn = (unsigned)(md.eoff + en) * NP + nn;
 #pragma unroll
-  for (int v = 0; v < NV; ++v) pr.nb.U[v] = (U + (size_t)v * N)[gn];
-  pr.nb.T = auxT[gn];
-  pr.nb.rvs = auxS[gn];
+  for (int v = 0; v < NV; ++v) pr.nb.U[v] = ld(U, N, v, gn);
+  pr.nb.T = ld(auxT, N, 0, gn);
+  pr.nb.rvs = ld(auxS, N, 0, gn);
   const int lz = (D == 2) ? (J == 0 ? fa : side * K) : (J == 2 ? side * K : fb);
   pr.izn = md.hoff + ((J == D - 1) ? cn * P1 + (side ? 0 : K) : ec.c[D - 1] * P1 + lz);
   pr.slot = le * NP + n;
@@ -393,7 +393,7 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
   constexpr int NV = V::NV;
   if (MODE == 0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = Rv[v];
+    for (int v = 0; v < NV; ++v) st(out, N, v, g, Rv[v]);
     return;
   }
   const R k2 = (R)(c2 * dtm);
@@ -408,7 +408,7 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
     for (int v = 0; v < NV; ++v) Un[v] = k1 * Uq[v] + k2 * Rv[v];
   }
 #pragma unroll
-  for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = Un[v];
+  for (int v = 0; v < NV; ++v) st(out, N, v, g, Un[v]);
   if (MODE == 2) {
     // split of the new state (FP64), warm-started at this node's (T, rho_vs);
     // bg = (rho_d, rho_m, rho_r, E) of the background at this node
@@ -431,8 +431,8 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
     const SplitOut s = split_point_anchor(a, rd, rm, rr, re, T, A, rvs < rm);
     iters = s.iters;
     bad = s.bad;
-    oT[g] = s.T;
-    oS[g] = (refresh && s.bad == 0) ? rho_vs(a, s.T) : s.rvs;
+    st(oT, N, 0, g, s.T);
+    st(oS, N, 0, g, (refresh && s.bad == 0) ? rho_vs(a, s.T) : s.rvs);
   }
 }
 
@@ -470,9 +470,9 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
   double T = 300.0, rvs = 0.0;
   if (active) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Uq[v] = (U + (size_t)v * N)[g];
-    T = auxT[g];
-    rvs = auxS[g];
+    for (int v = 0; v < NV; ++v) Uq[v] = ld(U, N, v, g);
+    T = ld(auxT, N, 0, g);
+    rvs = ld(auxS, N, 0, g);
   } else {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Uq[v] = R(0);
@@ -546,7 +546,7 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
   // the other wavefronts finish
   if (MODE != 0 && active && c0 != 0.0) {
 #pragma unroll
-    for (int v = 0; v < NV; ++v) U0q[v] = (U0 + (size_t)v * N)[g];
+    for (int v = 0; v < NV; ++v) U0q[v] = ld(U0, N, v, g);
   }
   if (MODE == 2 && active) {
     bg[0] = a.bg_rd[iz];
