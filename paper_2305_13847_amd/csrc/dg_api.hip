@@ -287,7 +287,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   h->prec = p->precision; h->rk = p->rk; h->nmembers = nmembers; h->P = *p;
   const int p1 = order + 1;
   h->np = dim == 2 ? p1 * p1 : p1 * p1 * p1;
-  const int epb = elems_per_block(order, dim);
+  const int epb = elems_per_block(order, dim, p->precision == DG_FP64);
   long long eoff = 0;
   int hoff = 0;
   long long items_max = 0;
@@ -772,7 +772,7 @@ static dg_status upload_items(dg_handle* h) {
 
 extern "C" dg_status dg_set_launch(dg_handle* h, int epb, int persist) {
   if (!h) return fail(DG_EINVAL, "null handle");
-  const int emax = elems_per_block(h->order, h->dim);
+  const int emax = elems_per_block(h->order, h->dim, h->prec == DG_FP64);
   if (epb < 1 || epb > emax) return fail(DG_EINVAL, "elements per block must be in 1..%d", emax);
   if (persist < 0 || persist > 64) return fail(DG_EINVAL, "persistent blocks per CU must be in 0..64");
   HIP_TRY(hipDeviceSynchronize());
@@ -802,7 +802,7 @@ extern "C" dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, 
   if (!U || !dt || nsteps < 1) return fail(DG_EINVAL, "bad autotune arguments");
   st = upload_dt(h, dt, 0);
   if (st != DG_OK) return st;
-  const int emax = elems_per_block(h->order, h->dim);
+  const int emax = elems_per_block(h->order, h->dim, h->prec == DG_FP64);
   const int cand_e[3] = {emax, emax / 2, emax / 4};
   const int cand_p[4] = {0, 1, 2, 4};
   void* W = h->stage_x[0];

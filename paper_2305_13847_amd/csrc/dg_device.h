@@ -18,11 +18,16 @@ struct Vars {
   static constexpr int RD = 0, RM = 1, RR = 2, M0 = 2 + RAIN, E = NV - 1;
 };
 
-template <int K, int D>
+// Threads per block: 256 in FP32; 128 in FP64, where the LDS tiles are twice
+// as large and 256-thread blocks would leave room for only two per CU.
+template <typename R>
+constexpr int block_threads() { return sizeof(R) == 4 ? 256 : 128; }
+
+template <int K, int D, int BT = 256>
 struct Shape {
   static constexpr int P1 = K + 1;
   static constexpr int NP = (D == 2) ? P1 * P1 : P1 * P1 * P1;
-  static constexpr int EPB = (256 / NP) > 0 ? 256 / NP : 1;   // elements per block
+  static constexpr int EPB = (BT / NP) > 0 ? BT / NP : 1;   // elements per block
   static constexpr int NT = EPB * NP;                          // threads per block
 };
 

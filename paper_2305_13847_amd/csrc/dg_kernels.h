@@ -77,7 +77,7 @@ template <typename R, int K, int D, int RAIN, int API>
 __global__ void __launch_bounds__(256)
 split_kernel(KArgs a, int item0, int nitems, const R* __restrict__ U, const double* __restrict__ Tguess,
              double* __restrict__ oT, double* __restrict__ o1, double* __restrict__ o2) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
   const ItemWalk walk(nitems);
@@ -150,7 +150,7 @@ __device__ __forceinline__ void gather_nb(const MemberDesc& md, const ElemCoord<
                                           const double* __restrict__ auxT,
                                           const double* __restrict__ auxS, unsigned N,
                                           Nb<R, D, RAIN>& nb, bool& wall, int& izn_off) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NV = V::NV;
   constexpr int STR = (J == 0) ? 1 : (J == 1 ? P1 : P1 * P1);
@@ -178,7 +178,7 @@ __device__ __forceinline__ void gather_nb(const MemberDesc& md, const ElemCoord<
 template <typename R, int K, int D, int RAIN, int J>
 __device__ __forceinline__ void volume_dir(const MemberDesc& md, int ij, const R* sFJ, R* Rv,
                                            const R* sD, int t = threadIdx.x) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NV = V::NV;
   constexpr int STR = (J == 0) ? 1 : (J == 1 ? P1 : P1 * P1);
@@ -201,7 +201,7 @@ template <typename R, int K, int D, int RAIN, int J>
 __device__ __forceinline__ void stage_flux(const Pt<R, D, RAIN>& q, R* sFJ) {
   using V = Vars<D, RAIN>;
   constexpr int NV = V::NV;
-  constexpr int NT = Shape<K, D>::NT;   // LDS row stride (the largest block)
+  constexpr int NT = Shape<K, D, block_threads<R>()>::NT;   // LDS row stride (the largest block)
   R F[NV];
   flux<R, D, RAIN, J>(q, F);
 #pragma unroll
@@ -354,7 +354,7 @@ __device__ __forceinline__ void pair_flux(const KArgs& a, const MemberDesc& md, 
                                           R* sF, const R* sU, const R* sL) {
   using V = Vars<D, RAIN>;
   constexpr int NV = V::NV;
-  constexpr int NT = Shape<K, D>::NT;
+  constexpr int NT = Shape<K, D, block_threads<R>()>::NT;
   if (pr.slot < 0) return;
   Pt<R, D, RAIN> qn;
   eval_point<R, D, RAIN>(a, pr.nb.U, pr.nb.T, pr.nb.rvs, pr.izn, qn);
@@ -448,7 +448,7 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
                                                const R* __restrict__ U0, const double* __restrict__ dt_m,
                                                double c0, double c1, double c2, double* __restrict__ oT,
                                                double* __restrict__ oS, int refresh) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   using FS = FaceShape<K, D>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV, NT = S::NT;
@@ -573,14 +573,14 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
 }
 
 template <typename R, int K, int D, int RAIN, int MODE>
-__device__ __forceinline__ void rhs_item(const KArgs& a, int it_, R (*sF)[Vars<D, RAIN>::NV * Shape<K, D>::NT],
+__device__ __forceinline__ void rhs_item(const KArgs& a, int it_, R (*sF)[Vars<D, RAIN>::NV * Shape<K, D, block_threads<R>()>::NT],
                                          const R* sD, const R* __restrict__ U,
                                          const double* __restrict__ auxT,
                                          const double* __restrict__ auxS, R* __restrict__ out,
                                          const R* __restrict__ U0, const double* __restrict__ dt_m,
                                          double c0, double c1, double c2, double* __restrict__ oT,
                                          double* __restrict__ oS, int refresh) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
   const int t = threadIdx.x;
@@ -701,7 +701,7 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
            const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
            const double* __restrict__ dt_m, double c0, double c1, double c2,
            double* __restrict__ oT, double* __restrict__ oS, int refresh) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1;
   constexpr bool PAIRS = K >= 2;
@@ -728,7 +728,7 @@ rhs_kernel_persistent(KArgs a, const KArgs* __restrict__ a_dev, const R* __restr
                       const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
                       const double* __restrict__ dt_m, double c0, double c1, double c2,
                       double* __restrict__ oT, double* __restrict__ oS, int refresh) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1;
   constexpr bool PAIRS = K >= 2;
@@ -771,7 +771,7 @@ template <typename R, int K, int D, int RAIN>
 __global__ void __launch_bounds__(256)
 mass_kernel(KArgs a, int item0, const R* __restrict__ U, double* __restrict__ partial) {
   // (blocks map to items in order here: partials are summed in a fixed order)
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP;
   __shared__ double sm[3][S::NT];

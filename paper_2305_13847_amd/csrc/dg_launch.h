@@ -29,9 +29,10 @@ inline int threads_per_block(int K, int D) {
   return epb * np;
 }
 
-inline int elems_per_block(int K, int D) {
-  int np = (D == 2) ? (K + 1) * (K + 1) : (K + 1) * (K + 1) * (K + 1);
-  return 256 / np > 0 ? 256 / np : 1;
+inline int elems_per_block(int K, int D, bool fp64) {
+  const int np = (D == 2) ? (K + 1) * (K + 1) : (K + 1) * (K + 1) * (K + 1);
+  const int bt = fp64 ? block_threads<double>() : block_threads<float>();
+  return bt / np > 0 ? bt / np : 1;
 }
 
 // Launch geometry of a handle: threads per block (EPB elements) and grid size.

@@ -324,7 +324,7 @@ rhs_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT
                const double* __restrict__ auxS, const R* __restrict__ lam, R* __restrict__ out,
                const R* __restrict__ X1, const R* __restrict__ X2, const double* __restrict__ dt_m,
                double cx1, double cx2, double c1, double c2) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
   __shared__ R sL[NV * S::NT];
@@ -445,7 +445,7 @@ split_vjp_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ au
                  const double* __restrict__ auxS, const double* __restrict__ Tbar,
                  const double* __restrict__ rvbar, const double* __restrict__ rcbar,
                  R* __restrict__ out) {
-  using S = Shape<K, D>;
+  using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
   const ItemWalk walk(a.nitems);

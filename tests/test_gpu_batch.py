@@ -81,7 +81,9 @@ def test_launch_geometry_does_not_change_results(prec):
     c = synth.warm_rain_3d(n=(6, 5, 4), order=3, seed=3)
     dtype = torch.float64 if prec == 0 else torch.float32
     outs = []
-    for epb, persist in [(4, 0), (2, 0), (1, 0), (4, 1), (2, 2), (1, 4)]:
+    emax = lib.for_case(c, precision=prec).get_launch()[0]      # 4 in FP32, 2 in FP64 (Q3 3D)
+    geos = [(emax, 0), (max(1, emax // 2), 0), (1, 0), (emax, 1), (max(1, emax // 2), 2), (1, 4)]
+    for epb, persist in geos:
         dg = lib.for_case(c, precision=prec)
         dg.set_launch(epb, persist)
         assert dg.get_launch() == (epb, persist)
