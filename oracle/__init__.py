@@ -29,7 +29,7 @@ class OraParams(ct.Structure):
     _fields_ = [(n, ct.c_double) for n in
                 ("g", "cvd", "cvv", "cl", "cpd", "cpv", "Rd", "Rv", "Lref", "Tref", "eref", "pref")] + \
                [("rain", ct.c_int), ("vr_mode", ct.c_int)] + \
-               [(n, ct.c_double) for n in ("vr_const", "rho_w", "N0r", "v0r", "q_au")]
+               [(n, ct.c_double) for n in ("vr_const", "rho_w", "N0r", "v0r", "q_au", "sponge_zD", "sponge_alpha")]
 
 
 class OraMesh(ct.Structure):
@@ -65,6 +65,9 @@ def lib():
         L.ora_rhs_jvp.argtypes = [ct.c_void_p, dp, dp, dp, dp]
         L.ora_rk_jvp.argtypes = [ct.c_void_p, dp, dp, ct.c_double, ct.c_int, ct.c_int]
         L.ora_mass.argtypes = [ct.c_void_p, dp, dp]
+        L.ora_sponge_delta.argtypes = [ct.c_void_p, ct.c_double]
+        L.ora_sponge_delta.restype = ct.c_double
+        L.ora_sponge_apply.argtypes = [ct.c_void_p, dp]
         L.ora_point.argtypes = [ct.c_void_p, dp, ct.c_int, dp, dp, dp]
         L.ora_face.argtypes = [ct.c_void_p, dp, ct.c_int, dp, ct.c_int, ct.c_int, dp]
         L.ora_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_long), ct.POINTER(ct.c_int),
@@ -190,6 +193,16 @@ class Oracle:
         out = np.zeros(3)
         lib().ora_mass(self.h, _p(U), _p(out))
         return out
+
+    def sponge_delta(self, z: float) -> float:
+        """Blending function of the sponge layer at height z."""
+        return lib().ora_sponge_delta(self.h, float(z))
+
+    def sponge(self, U: np.ndarray) -> np.ndarray:
+        """The end-of-step sponge applied once to a copy of U."""
+        U = np.array(U, dtype=np.float64, copy=True, order="C")
+        lib().ora_sponge_apply(self.h, _p(U))
+        return U
 
     def point(self, Uq: np.ndarray, iz: int):
         Uq = np.ascontiguousarray(Uq, dtype=np.float64)

@@ -98,6 +98,9 @@ struct OraParams {
   int rain;        // 0: no rain (nvars = 3 + d), 1: Kessler warm rain (4 + d)
   int vr_mode;     // 0: constant v_r, 1: COSMO formula
   double vr_const, rho_w, N0r, v0r, q_au;
+  // Rayleigh sponge (Section 3, explicit sponge layer): bottom height z_D and
+  // strength alpha of the blending function; alpha = 0 switches it off
+  double sponge_zD, sponge_alpha;
 };
 
 struct OraMesh {
@@ -117,6 +120,7 @@ void ora_default_params(OraParams* p) {
   p->rain = 0; p->vr_mode = 0; p->vr_const = 5.0;
   // COSMO warm-rain distribution parameters (Section 2.1)
   p->rho_w = 1000.0; p->N0r = 8.0e6; p->v0r = 130.0; p->q_au = 0.0;
+  p->sponge_zD = 0.0; p->sponge_alpha = 0.0;
 }
 
 }  // extern "C"
@@ -524,8 +528,45 @@ template <class R> void rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
   if (wall_rain_flux) *wall_rain_flux = wflux;
 }
 
+// Blending function of the sponge layer (Section 3, explicit sponge layer):
+// delta(z) = alpha/2 (1 - cos(pi (z - z_D)/(z_T - z_D))) above z_D, 0 below,
+// with z_T the top of the domain.
+double sponge_delta(const Ctx& c, double z) {
+  const double zD = c.P.sponge_zD, zT = c.M.hi[c.d - 1];
+  if (!(c.P.sponge_alpha > 0.0) || z < zD) return 0.0;
+  return 0.5 * c.P.sponge_alpha * (1.0 - std::cos(M_PI * (z - zD) / (zT - zD)));
+}
+
+// height of node n of element e
+double node_z(const Ctx& c, int e, int n) {
+  const int a = c.d - 1;
+  return c.M.lo[a] + c.h[a] * (elem_axis(c, e, a) + 0.5 * (1.0 + c.tab.x[node_axis(n, a, c.k + 1)]));
+}
+
+// The sponge at the end of a time step, node by node (with Lobatto
+// collocation the L2 projection of the product is its nodal value): the
+// moist perturbations, the momentum and E' relax towards the far field
+// (0, 0, rho u_bar = 0, 0), U = (1 - delta) U_pred + delta U_far, and the
+// moist mass removed is added to rho_d' at the same node, so the total
+// density is unchanged.
+template <class R> void sponge(Ctx& c, R* U) {
+  if (!(c.P.sponge_alpha > 0.0)) return;
+  const long N = (long)c.ne * c.np;
+  for (int e = 0; e < c.ne; ++e)
+    for (int n = 0; n < c.np; ++n) {
+      const double dl = sponge_delta(c, node_z(c, e, n));
+      if (dl == 0.0) continue;
+      const long i = (long)e * c.np + n;
+      R lost = U[v_rm() * N + i] * dl;
+      if (c.P.rain) lost = lost + U[v_rr(c) * N + i] * dl;
+      for (int v = 1; v < c.nvars; ++v) U[v * N + i] = U[v * N + i] * (1.0 - dl);
+      U[v_rd() * N + i] = U[v_rd() * N + i] + lost;
+    }
+}
+
 // SSP Runge-Kutta step in Shu-Osher form (Section 3.3 remark): SSPRK(4,3) of
-// Kraaijevanger, or the three-stage SSPRK(3,3).
+// Kraaijevanger, or the three-stage SSPRK(3,3); the sponge, when on, closes
+// the step.
 template <class R> void rk_step(Ctx& c, R* U, double dt, int scheme, double* outflow) {
   const long N = (long)c.ne * c.np * c.nvars;
   std::vector<R> u0(U, U + N), us(N), L(N);
@@ -551,6 +592,7 @@ template <class R> void rk_step(Ctx& c, R* U, double dt, int scheme, double* out
     rhs(c, us.data(), L.data(), &f); fl += f * (2.0 / 3.0);
     for (long i = 0; i < N; ++i) U[i] = (1.0 / 3.0) * u0[i] + (2.0 / 3.0) * us[i] + ((2.0 / 3.0) * dt) * L[i];
   }
+  sponge(c, U);
   if (outflow) *outflow = fl * dt;
 }
 
@@ -698,6 +740,10 @@ int ora_rk_jvp(void* h, double* U, double* V, double dt, int nsteps, int scheme)
   for (long i = 0; i < N; ++i) { U[i] = Ud[i].v; V[i] = Ud[i].d; }
   return c->bad - bad;
 }
+
+// sponge blending function at height z, and the sponge applied once to U
+double ora_sponge_delta(void* h, double z) { return sponge_delta(*(Ctx*)h, z); }
+void ora_sponge_apply(void* h, double* U) { sponge(*(Ctx*)h, U); }
 
 // M_d = sum w J rho_d', M_w = sum w J (rho_m' + rho_r'), and the instantaneous
 // rain mass flux out through the walls

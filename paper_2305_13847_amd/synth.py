@@ -319,13 +319,14 @@ def periodic_smooth(n=(16, 16), order=2, seed=1, nsteps=10, sat_fraction=0.3,
 
 
 def moist_bubble(n=(128, 64), order=4, seed=2, nsteps=1000, amp=2.0, centre=(10e3, 2e3),
-                 radius=2e3, noise=1e-4, ratio=1.3, Ts=300.0) -> Case:
+                 radius=2e3, noise=1e-4, ratio=1.3, Ts=300.0, top=10e3) -> Case:
     """2D moist rising bubble in a cloudy background (Bryan-Fritsch shape).
 
-    Domain 20 km x 10 km, periodic in x, slip walls in z, gravity on, no rain.
+    Domain 20 km x `top` (10 km), periodic in x, slip walls in z, gravity on,
+    no rain.
     """
     rng = np.random.default_rng(seed)
-    mesh = Mesh(2, list(n), [0.0, 0.0], [20e3, 10e3], [PERIODIC, WALL], order)
+    mesh = Mesh(2, list(n), [0.0, 0.0], [20e3, top], [PERIODIC, WALL], order)
     bgf = background(mesh, Ts, lambda z: ratio + 0.0 * z)
     X = node_coords(mesh)
     th = bubble(X, centre, radius, amp)
