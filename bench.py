@@ -9,8 +9,9 @@ stages / wall time) with the state resident in HBM.
 
 Also reported on the same line: the roofline of the dominant kernel (the fused
 stage kernel: algorithmic bytes per launch / its HIP-event-timed duration
-against 8 TB/s), the FP64 run of the same workload, the 2D moist bubble
-(128 x 64, Q4) in FP64 and FP32, and the FP64 CPU reference timed on a bounded
+against 8 TB/s), the FP64 run of the same workload, the same FP32 workload
+with the Rayleigh sponge layer on, the 2D moist bubble (128 x 64, Q4) in FP64
+and FP32, the batched ensemble, and the FP64 CPU reference timed on a bounded
 sample of the 3D workload.
 """
 from __future__ import annotations
@@ -52,8 +53,8 @@ def traffic_for(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
-def time_workload(case, precision, steps, warmup, lib, torch, kernel_timing=True):
-    dg = lib.for_case(case, precision=precision)
+def time_workload(case, precision, steps, warmup, lib, torch, kernel_timing=True, **over):
+    dg = lib.for_case(case, precision=precision, **over)
     dt = torch.float64 if precision == lib.DG_FP64 else torch.float32
     U = torch.tensor(case.U, dtype=dt, device="cuda").contiguous()
     dofs = case.U.size
@@ -177,6 +178,11 @@ def main():
     if not args.no_extra:
         r64 = time_workload(case, lib.DG_FP64, max(2, args.steps // 4), 1, lib, torch)
         extra["rain3d_fp64"] = {k: r64[k] for k in ("dof_stage_per_s", "ms_per_step", "stage_us", "split_us")}
+        # the same FP32 workload with the Rayleigh sponge above 7 km, fused into
+        # the last stage of every step
+        rsp = time_workload(case, lib.DG_FP32_BULK, args.steps, args.warmup, lib, torch,
+                            sponge_zD=7.0e3, sponge_alpha=0.5)
+        extra["rain3d_fp32_sponge"] = {k: rsp[k] for k in ("dof_stage_per_s", "ms_per_step", "stage_us")}
         del case
         bub = synth.moist_bubble()
         for prec, nm in ((lib.DG_FP64, "bubble2d_q4_fp64"), (lib.DG_FP32_BULK, "bubble2d_q4_fp32")):

@@ -92,6 +92,14 @@ typedef struct {
   int rk;                     /* DG_SSPRK43 (default) or DG_SSPRK33            */
   double newton_rtol;         /* split stops when |dT| <= rtol * T (1e-14)     */
   int newton_maxit;           /* iteration cap (30); counted as non-converged  */
+  /* Rayleigh sponge layer (Section 3.6): at the end of
+   * every RK step, (rho_m', rho_r', m, E') <- (1 - delta(z)) (rho_m', rho_r',
+   * m, E') with delta(z) = alpha/2 (1 - cos(pi (z - zD)/(zT - zD))) above zD
+   * (zT the member's top, far-field velocity 0), and the moist mass removed
+   * is added to rho_d' at the same node.  alpha = 0 (default) switches it
+   * off; 0 < alpha <= 1 and zD below every member's top otherwise. */
+  double sponge_zD;           /* m, bottom of the sponge layer                 */
+  double sponge_alpha;        /* strength in [0, 1]                             */
 } dg_params;
 
 typedef struct {
@@ -101,7 +109,7 @@ typedef struct {
   int nonfinite;              /* 1 if a non-finite or invalid state was seen   */
 } dg_stats;
 
-/* Fill *p with the paper's constants, no rain, FP64, SSPRK(4,3). */
+/* Fill *p with the paper's constants, no rain, FP64, SSPRK(4,3), no sponge. */
 void dg_default_params(dg_params* p);
 
 /* Create a handle for one mesh.  order k in 1..4, nvars = 3 + dim (rain = 0)

@@ -98,7 +98,7 @@ struct OraParams {
   int rain;        // 0: no rain (nvars = 3 + d), 1: Kessler warm rain (4 + d)
   int vr_mode;     // 0: constant v_r, 1: COSMO formula
   double vr_const, rho_w, N0r, v0r, q_au;
-  // Rayleigh sponge (Section 3, explicit sponge layer): bottom height z_D and
+  // Rayleigh sponge (Section 3.6): bottom height z_D and
   // strength alpha of the blending function; alpha = 0 switches it off
   double sponge_zD, sponge_alpha;
 };
@@ -528,7 +528,7 @@ template <class R> void rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
   if (wall_rain_flux) *wall_rain_flux = wflux;
 }
 
-// Blending function of the sponge layer (Section 3, explicit sponge layer):
+// Blending function of the sponge layer (Section 3.6):
 // delta(z) = alpha/2 (1 - cos(pi (z - z_D)/(z_T - z_D))) above z_D, 0 below,
 // with z_T the top of the domain.
 double sponge_delta(const Ctx& c, double z) {

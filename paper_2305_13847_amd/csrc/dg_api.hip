@@ -68,6 +68,9 @@ struct dg_handle {
   double* bg_d[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // rd, rm, rr, E, p
   void* stage[2] = {nullptr, nullptr};
   void* stage_x[4] = {nullptr, nullptr, nullptr, nullptr};          // adjoint workspace
+  void* stage_w = nullptr;       // adjoint of the step's end state through the sponge
+  double* sponge_d = nullptr;    // sponge blending factor per vertical node index
+  bool sponge = false;
   double* auxT = nullptr;
   double* auxS = nullptr;
   double* auxT2 = nullptr;
@@ -162,14 +165,18 @@ static double legendre_P(int k, double x) {
   return p1;
 }
 
-static void lobatto_tables(int k, double* w, double* Dhat) {
-  double x[kMaxP1];
+static void lobatto_nodes(int k, double* x) {
   switch (k) {
     case 1: x[0] = -1; x[1] = 1; break;
     case 2: x[0] = -1; x[1] = 0; x[2] = 1; break;
     case 3: x[0] = -1; x[1] = -1 / std::sqrt(5.0); x[2] = -x[1]; x[3] = 1; break;
     default: x[0] = -1; x[1] = -std::sqrt(3.0 / 7.0); x[2] = 0; x[3] = -x[1]; x[4] = 1; break;
   }
+}
+
+static void lobatto_tables(int k, double* w, double* Dhat) {
+  double x[kMaxP1];
+  lobatto_nodes(k, x);
   const int p1 = k + 1;
   double P[kMaxP1];
   for (int i = 0; i < p1; ++i) {
@@ -194,6 +201,7 @@ static void free_all(dg_handle* h) {
   for (auto& b : h->bg_d) F(b);
   for (auto& b : h->stage) F(b);
   for (auto& b : h->stage_x) F(b);
+  F(h->stage_w); F(h->sponge_d);
   F(h->auxT); F(h->auxS); F(h->auxT2); F(h->auxS2);
   F(h->auxT3); F(h->auxS3); F(h->auxT4); F(h->auxS4);
   F(h->dt_d); F(h->partial); F(h->red_out); F(h->stats);
@@ -278,6 +286,12 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   if (p->rk != DG_SSPRK43 && p->rk != DG_SSPRK33) return fail(DG_EINVAL, "bad rk scheme");
   if (p->vr_mode != DG_VR_CONST && p->vr_mode != DG_VR_COSMO) return fail(DG_EINVAL, "bad vr_mode");
   if (!(p->newton_rtol > 0) || p->newton_maxit < 1) return fail(DG_EINVAL, "bad Newton settings");
+  if (!(p->sponge_alpha >= 0.0 && p->sponge_alpha <= 1.0) || !std::isfinite(p->sponge_zD))
+    return fail(DG_EINVAL, "sponge_alpha must lie in [0, 1] and sponge_zD be finite");
+  if (p->sponge_alpha > 0.0)
+    for (int m = 0; m < nmembers; ++m)
+      if (!(p->sponge_zD < meshes[m].hi[dim - 1]))
+        return fail(DG_EINVAL, "sponge_zD must lie below the top of member %d", m);
   for (int m = 0; m < nmembers; ++m) {
     dg_status s = validate_mesh(&meshes[m], dim);
     if (s != DG_OK) return s;
@@ -359,6 +373,11 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   ok = ok && A((void**)&h->auxT4, sizeof(double) * h->nnodes);
   ok = ok && A((void**)&h->auxS4, sizeof(double) * h->nnodes);
   for (auto& b : h->stage_x) ok = ok && A(&b, h->state_bytes);
+  h->sponge = p->sponge_alpha > 0.0;
+  if (h->sponge) {
+    ok = ok && A(&h->stage_w, h->state_bytes);
+    ok = ok && A((void**)&h->sponge_d, sizeof(double) * hoff);
+  }
   ok = ok && A((void**)&h->dt_d, sizeof(double) * nmembers);
   ok = ok && A((void**)&h->partial, sizeof(double) * 3 * h->items_cap);
   ok = ok && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) == hipSuccess;
@@ -407,6 +426,32 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   a.bg_rd = h->bg_d[0]; a.bg_rm = h->bg_d[1]; a.bg_rr = h->bg_d[2]; a.bg_E = h->bg_d[3];
   a.bg_p = h->bg_d[4];
   a.stats = h->stats;
+  a.sponge = nullptr;
+  if (h->sponge) {
+    // blending factor at every node height of every member (the L2 projection
+    // onto the Lobatto nodal basis is the nodal value)
+    double xl[kMaxP1];
+    lobatto_nodes(order, xl);
+    std::vector<double> dl(hoff, 0.0);
+    for (int m = 0; m < nmembers; ++m) {
+      const dg_mesh& g = meshes[m];
+      const int az = dim - 1;
+      const double hz = (g.hi[az] - g.lo[az]) / g.n[az];
+      const double zD = p->sponge_zD, zT = g.hi[az];
+      for (int c = 0; c < g.n[az]; ++c)
+        for (int l = 0; l <= order; ++l) {
+          const double z = g.lo[az] + hz * (c + 0.5 * (1.0 + xl[l]));
+          dl[h->hoff[m] + c * (order + 1) + l] =
+              z < zD ? 0.0 : 0.5 * p->sponge_alpha * (1.0 - std::cos(M_PI * (z - zD) / (zT - zD)));
+        }
+    }
+    if (hipMemcpy(h->sponge_d, dl.data(), sizeof(double) * hoff, hipMemcpyHostToDevice) != hipSuccess) {
+      free_all(h);
+      delete h;
+      return fail(DG_EHIP, "initial upload failed");
+    }
+    a.sponge = h->sponge_d;
+  }
   if (hipMemcpy(h->ka_d, &h->ka, sizeof(KArgs), hipMemcpyHostToDevice) != hipSuccess) {
     free_all(h);
     delete h;
@@ -496,15 +541,15 @@ static bool do_split(dg_handle* h, const void* U, const double* guess, double* o
 
 static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, const double* aS, void* out,
                    const void* U0, double c0, double c1, double c2, hipStream_t s,
-                   double* oT = nullptr, double* oS = nullptr, int refresh = 0) {
+                   double* oT = nullptr, double* oS = nullptr, int flags = 0) {
   KTimer kt(h, DG_K_STAGE, s);
   if (mode == 2) h->splits += h->nnodes;
   const LaunchCfg lc = launch_cfg(h);
   if (h->prec == DG_FP64)
     return Launch<double>::rhs(h->ka, h->ka_d, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0,
-                               h->dt_d, c0, c1, c2, oT, oS, refresh, s);
+                               h->dt_d, c0, c1, c2, oT, oS, flags, s);
   return Launch<float>::rhs(h->ka, h->ka_d, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d,
-                            c0, c1, c2, oT, oS, refresh, s);
+                            c0, c1, c2, oT, oS, flags, s);
 }
 
 extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t s) {
@@ -567,8 +612,11 @@ static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t
     void* outp = h->rk == DG_SSPRK43 ? out43[st] : out33[st];
     const int a = *cur, b = 1 - *cur;
     // the stored rho_vs(T) anchors the next split; it is evaluated afresh at
-    // the last stage of every fourth step so series updates never chain long
-    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], st == ns - 1 && (step & 3) == 3);
+    // the last stage of every fourth step so series updates never chain long;
+    // the last stage ends the step and applies the sponge
+    const bool last = st == ns - 1;
+    const int flags = (last && (step & 3) == 3 ? kRefreshRvs : 0) | (last && h->sponge ? kSponge : 0);
+    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], flags);
     *cur = b;
   }
   HIP_TRY(hipGetLastError());
@@ -716,22 +764,31 @@ extern "C" dg_status dg_rk_step_vjp(dg_handle* h, const void* Un, const void* W,
   void* B3 = h->stage_x[3];
   double* aT[4] = {h->auxT, h->auxT2, h->auxT3, h->auxT4};
   double* aS[4] = {h->auxS, h->auxS2, h->auxS3, h->auxS4};
+  // the step ends with the sponge: its transpose acts first
+  const void* Wt = W;
+  if (h->sponge) {
+    const LaunchCfg lc = launch_cfg(h);
+    KTimer kt(h, DG_K_ADJOINT, s);
+    if (h->prec == DG_FP64) Launch<double>::sponge_vjp(h->ka, lc, h->order, h->dim, h->rain, W, h->stage_w, s);
+    else Launch<float>::sponge_vjp(h->ka, lc, h->order, h->dim, h->rain, W, h->stage_w, s);
+    Wt = h->stage_w;
+  }
   // recompute the stages
   do_split(h, Un, nullptr, aT[0], aS[0], nullptr, 0, s);
   if (h->rk == DG_SSPRK43) {
     do_rhs(h, 2, Un, aT[0], aS[0], u1, Un, kSSP43[0].c0, kSSP43[0].c1, kSSP43[0].c2, s, aT[1], aS[1], 0);
     do_rhs(h, 2, u1, aT[1], aS[1], u2, Un, kSSP43[1].c0, kSSP43[1].c1, kSSP43[1].c2, s, aT[2], aS[2], 0);
     do_rhs(h, 2, u2, aT[2], aS[2], u3, Un, kSSP43[2].c0, kSSP43[2].c1, kSSP43[2].c2, s, aT[3], aS[3], 0);
-    do_vjp(h, u3, aT[3], aS[3], W, B3, nullptr, nullptr, h->dt_d, 0, 0, 1.0, 0.5, s);
+    do_vjp(h, u3, aT[3], aS[3], Wt, B3, nullptr, nullptr, h->dt_d, 0, 0, 1.0, 0.5, s);
     do_vjp(h, u2, aT[2], aS[2], B3, B2, nullptr, nullptr, h->dt_d, 0, 0, 1.0 / 3.0, 1.0 / 6.0, s);
     do_vjp(h, u1, aT[1], aS[1], B2, B1, nullptr, nullptr, h->dt_d, 0, 0, 1.0, 0.5, s);
     do_vjp(h, Un, aT[0], aS[0], B1, Ub0, B3, nullptr, h->dt_d, 2.0 / 3.0, 0, 1.0, 0.5, s);
   } else {
     do_rhs(h, 2, Un, aT[0], aS[0], u1, Un, kSSP33[0].c0, kSSP33[0].c1, kSSP33[0].c2, s, aT[1], aS[1], 0);
     do_rhs(h, 2, u1, aT[1], aS[1], u2, Un, kSSP33[1].c0, kSSP33[1].c1, kSSP33[1].c2, s, aT[2], aS[2], 0);
-    do_vjp(h, u2, aT[2], aS[2], W, B2, nullptr, nullptr, h->dt_d, 0, 0, 2.0 / 3.0, 2.0 / 3.0, s);
+    do_vjp(h, u2, aT[2], aS[2], Wt, B2, nullptr, nullptr, h->dt_d, 0, 0, 2.0 / 3.0, 2.0 / 3.0, s);
     do_vjp(h, u1, aT[1], aS[1], B2, B1, nullptr, nullptr, h->dt_d, 0, 0, 0.25, 0.25, s);
-    do_vjp(h, Un, aT[0], aS[0], B1, Ub0, W, B2, h->dt_d, 1.0 / 3.0, 0.75, 1.0, 1.0, s);
+    do_vjp(h, Un, aT[0], aS[0], B1, Ub0, Wt, B2, h->dt_d, 1.0 / 3.0, 0.75, 1.0, 1.0, s);
   }
   HIP_TRY(hipGetLastError());
   return DG_OK;

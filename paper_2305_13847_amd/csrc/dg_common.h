@@ -58,6 +58,8 @@ struct KArgs {
   const double* bg_rr;
   const double* bg_E;
   const double* bg_p;
+  // sponge blending factor per vertical node index (nullptr: no sponge)
+  const double* sponge;
   // status words: [0] max iterations, [1] non-converged, [2] invalid, [3] spare,
   // [4..5] split count (64-bit)
   unsigned* stats;

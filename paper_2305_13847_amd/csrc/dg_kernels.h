@@ -70,6 +70,26 @@ struct ItemWalk {
 
 __host__ __device__ inline int grid_for_items(int nitems) { return ((nitems + 7) >> 3) << 3; }
 
+// flags of a stage launch
+constexpr int kRefreshRvs = 1;   // store a fresh rho_vs(T) evaluation (anchors later splits)
+constexpr int kSponge = 2;       // the stage ends a time step: apply the sponge
+
+// The sponge at the end of a step (Section 3.6):
+// (rho_m', rho_r', m, E') <- (1 - delta) (rho_m', rho_r', m, E') with the
+// far field at rest, and the moist mass removed goes to rho_d' at the node.
+template <typename R, int D, int RAIN>
+__device__ __forceinline__ void sponge_point(const KArgs& a, int iz, R* Un) {
+  using V = Vars<D, RAIN>;
+  const R dl = (R)a.sponge[iz];
+  if (dl == R(0)) return;
+  R lost = Un[V::RM] * dl;
+  if (RAIN) lost = lost + Un[V::RR] * dl;
+  const R keep = R(1) - dl;
+#pragma unroll
+  for (int v = 1; v < V::NV; ++v) Un[v] = Un[v] * keep;
+  Un[V::RD] = Un[V::RD] + lost;
+}
+
 // ---------------------------------------------------------------------------
 // split kernel: (T, rho_vs) per node, or the API outputs (T, rho_v, rho_c)
 // ---------------------------------------------------------------------------
@@ -136,8 +156,10 @@ split_kernel(KArgs a, int item0, int nitems, const R* __restrict__ U, const doub
 // MODE 1: out = c0 U0 + c1 U + c2 dt_member dU/dt  (a Shu-Osher stage)
 // MODE 2: as MODE 1, then the split of the new state at every node, written
 //         to (oT, oS); Newton is warm-started and anchored at the input
-//         state's (T, rho_vs).  With `refresh` the stored rho_vs is a fresh
+//         state's (T, rho_vs).  With kRefreshRvs the stored rho_vs is a fresh
 //         evaluation at the new T (once per step), otherwise the anchored one.
+// With kSponge (MODE 1, 2) the new state is the end of a step: the sponge
+// acts on it before it is stored and split.
 template <typename R, int D, int RAIN>
 struct Nb {
   R U[Vars<D, RAIN>::NV];
@@ -384,11 +406,11 @@ __device__ __forceinline__ void pair_flux_rt(int J, const KArgs& a, const Member
 
 // Stage update and the split epilogue shared by both face schemes.
 template <typename R, int D, int RAIN, int MODE>
-__device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg, unsigned g, unsigned N,
+__device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg, int iz, unsigned g, unsigned N,
                                                const R* Uq, const R* U0q, const R* Rv, double T, double rvs,
                                                R* __restrict__ out, double dtm, double c0, double c1,
                                                double c2, double* __restrict__ oT,
-                                               double* __restrict__ oS, int refresh, int& iters, int& bad) {
+                                               double* __restrict__ oS, int flags, int& iters, int& bad) {
   using V = Vars<D, RAIN>;
   constexpr int NV = V::NV;
   if (MODE == 0) {
@@ -407,6 +429,7 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
 #pragma unroll
     for (int v = 0; v < NV; ++v) Un[v] = k1 * Uq[v] + k2 * Rv[v];
   }
+  if (flags & kSponge) sponge_point<R, D, RAIN>(a, iz, Un);
 #pragma unroll
   for (int v = 0; v < NV; ++v) st(out, N, v, g, Un[v]);
   if (MODE == 2) {
@@ -432,7 +455,7 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
     iters = s.iters;
     bad = s.bad;
     st(oT, N, 0, g, s.T);
-    st(oS, N, 0, g, (refresh && s.bad == 0) ? rho_vs(a, s.T) : s.rvs);
+    st(oS, N, 0, g, ((flags & kRefreshRvs) && s.bad == 0) ? rho_vs(a, s.T) : s.rvs);
   }
 }
 
@@ -447,7 +470,7 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
                                                const double* __restrict__ auxS, R* __restrict__ out,
                                                const R* __restrict__ U0, const double* __restrict__ dt_m,
                                                double c0, double c1, double c2, double* __restrict__ oT,
-                                               double* __restrict__ oS, int refresh) {
+                                               double* __restrict__ oS, int flags) {
   using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   using FS = FaceShape<K, D>;
@@ -566,7 +589,7 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
     R Us[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Us[v] = sU[v * NT + t];
-    stage_epilogue<R, D, RAIN, MODE>(a, bg, g, N, Us, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS, refresh,
+    stage_epilogue<R, D, RAIN, MODE>(a, bg, iz, g, N, Us, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS, flags,
                                      iters, bad);
   }
   if (MODE == 2) record_stats(a, iters, bad);
@@ -579,7 +602,7 @@ __device__ __forceinline__ void rhs_item(const KArgs& a, int it_, R (*sF)[Vars<D
                                          const double* __restrict__ auxS, R* __restrict__ out,
                                          const R* __restrict__ U0, const double* __restrict__ dt_m,
                                          double c0, double c1, double c2, double* __restrict__ oT,
-                                         double* __restrict__ oS, int refresh) {
+                                         double* __restrict__ oS, int flags) {
   using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
@@ -657,6 +680,7 @@ __device__ __forceinline__ void rhs_item(const KArgs& a, int it_, R (*sF)[Vars<D
 #pragma unroll
         for (int v = 0; v < NV; ++v) Un[v] = k1 * Uq[v] + k2 * Rv[v];
       }
+      if (MODE != 0 && (flags & kSponge)) sponge_point<R, D, RAIN>(a, iz, Un);
 #pragma unroll
       for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = Un[v];
       if (MODE == 2) {
@@ -681,7 +705,7 @@ __device__ __forceinline__ void rhs_item(const KArgs& a, int it_, R (*sF)[Vars<D
         iters = s.iters;
         bad = s.bad;
         oT[g] = s.T;
-        oS[g] = (refresh && s.bad == 0) ? rho_vs(a, s.T) : s.rvs;
+        oS[g] = ((flags & kRefreshRvs) && s.bad == 0) ? rho_vs(a, s.T) : s.rvs;
       }
     }
   }
@@ -700,7 +724,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_wa
 rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
            const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
            const double* __restrict__ dt_m, double c0, double c1, double c2,
-           double* __restrict__ oT, double* __restrict__ oS, int refresh) {
+           double* __restrict__ oT, double* __restrict__ oS, int flags) {
   using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1;
@@ -715,9 +739,9 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   if (it_ < 0) return;
   if constexpr (PAIRS)
     rhs_item_pairs<R, K, D, RAIN, MODE>(
-        a, threadIdx.x, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
+        a, threadIdx.x, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, flags);
   else
-    rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
+    rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, flags);
 }
 
 // persistent: a grid smaller than the item count walks the items
@@ -727,7 +751,7 @@ rhs_kernel_persistent(KArgs a, const KArgs* __restrict__ a_dev, const R* __restr
                       const double* __restrict__ auxT,
                       const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
                       const double* __restrict__ dt_m, double c0, double c1, double c2,
-                      double* __restrict__ oT, double* __restrict__ oS, int refresh) {
+                      double* __restrict__ oT, double* __restrict__ oS, int flags) {
   using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1;
@@ -755,9 +779,9 @@ rhs_kernel_persistent(KArgs a, const KArgs* __restrict__ a_dev, const R* __restr
     asm volatile("" : "+v"(t));
     if constexpr (PAIRS)
       rhs_item_pairs<R, K, D, RAIN, MODE>(*ap, t, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m,
-                                             c0, c1, c2, oT, oS, refresh);
+                                             c0, c1, c2, oT, oS, flags);
     else
-      rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, refresh);
+      rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, flags);
     __syncthreads();   // the LDS tiles are reused by the next item
   }
 }
@@ -824,6 +848,44 @@ mass_kernel(KArgs a, int item0, const R* __restrict__ U, double* __restrict__ pa
     partial[3 * blockIdx.x + 0] = sm[0][0];
     partial[3 * blockIdx.x + 1] = sm[1][0];
     partial[3 * blockIdx.x + 2] = sm[2][0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// transpose of the end-of-step sponge (the adjoint of dg_rk_step)
+// ---------------------------------------------------------------------------
+// Wp = S^T W for the pointwise sponge map S of sponge_point:
+//   Wp[rho_d] = W[rho_d],  Wp[rho_m] = (1 - delta) W[rho_m] + delta W[rho_d],
+//   Wp[rho_r] = (1 - delta) W[rho_r] + delta W[rho_d],  Wp[v] = (1 - delta) W[v]
+//   for the momentum and E'.
+template <typename R, int K, int D, int RAIN>
+__global__ void __launch_bounds__(256)
+sponge_vjp_kernel(KArgs a, const R* __restrict__ W, R* __restrict__ Wp) {
+  using S = Shape<K, D, block_threads<R>()>;
+  using V = Vars<D, RAIN>;
+  constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
+  const ItemWalk walk(a.nitems);
+  for (int k = 0;; ++k) {
+    const int it_ = walk.item(k);
+    if (it_ < 0) break;
+    const int t = threadIdx.x;
+    const Item item = a.items[it_];
+    const MemberDesc& md = a.mem[item.member];
+    const int le = t / NP, n = t - le * NP;
+    const int e = item.e0 + le;
+    if (e >= md.ne) continue;
+    const unsigned N = a.nnodes;
+    const unsigned g = (unsigned)(md.eoff + e) * NP + n;
+    const ElemCoord<D> ec = item_coord<D>(md, item, le);
+    const int l = (D == 2) ? n / P1 : n / (P1 * P1);
+    const R dl = (R)a.sponge[md.hoff + ec.c[D - 1] * P1 + l];
+    const R keep = R(1) - dl;
+    const R wd = ld(W, N, V::RD, g);
+    st(Wp, N, V::RD, g, wd);
+    st(Wp, N, V::RM, g, keep * ld(W, N, V::RM, g) + dl * wd);
+    if (RAIN) st(Wp, N, V::RR, g, keep * ld(W, N, V::RR, g) + dl * wd);
+#pragma unroll
+    for (int v = V::M0; v < NV; ++v) st(Wp, N, v, g, keep * ld(W, N, v, g));
   }
 }
 

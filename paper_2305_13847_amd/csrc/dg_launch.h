@@ -65,13 +65,13 @@ struct Launch {
   static bool rhs(const KArgs& a, const KArgs* a_dev, LaunchCfg lc, int K, int D, int rain, int mode, const void* U,
                   const double* auxT, const double* auxS, void* out, const void* U0,
                   const double* dt, double c0, double c1, double c2, double* oT, double* oS,
-                  int refresh, hipStream_t s) {
+                  int flags, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
       dim3 grid(lc.grid), block(lc.threads);
 #define DGM_RHS(KER, M)                                                                           \
   hipLaunchKernelGGL((KER<R, K_, D_, R_, M>), grid, block, 0, s, a, (const R*)U, auxT, auxS,       \
-                     (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, refresh)
+                     (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, flags)
       // the persistent (looping) variant only when the grid is smaller than the items
       const bool persist = (int)grid.x < grid_for_items(a.nitems);
       if (mode == 0) DGM_RHS(rhs_kernel, 0);
@@ -79,8 +79,17 @@ struct Launch {
       else if (!persist) DGM_RHS(rhs_kernel, 2);
       else
         hipLaunchKernelGGL((rhs_kernel_persistent<R, K_, D_, R_, 2>), grid, block, 0, s, a, a_dev, (const R*)U,
-                           auxT, auxS, (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, refresh);
+                           auxT, auxS, (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, flags);
 #undef DGM_RHS
+    });
+  }
+
+  static bool sponge_vjp(const KArgs& a, LaunchCfg lc, int K, int D, int rain, const void* W, void* Wp,
+                         hipStream_t s) {
+    return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
+      constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
+      hipLaunchKernelGGL((sponge_vjp_kernel<R, K_, D_, R_>), dim3(lc.grid), dim3(lc.threads), 0, s, a,
+                         (const R*)W, (R*)Wp);
     });
   }
 

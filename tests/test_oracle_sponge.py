@@ -1,4 +1,4 @@
-"""Pins of the reference's sponge layer (Section 3, explicit sponge layer).
+"""Pins of the reference's sponge layer (Section 3.6).
 
 The blending function is checked at the points where its value is fixed:
 - 0 below z_D and continuous there with zero slope;
