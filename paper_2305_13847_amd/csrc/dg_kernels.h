@@ -779,7 +779,7 @@ rhs_kernel_persistent(KArgs a, const KArgs* __restrict__ a_dev, const R* __restr
     asm volatile("" : "+v"(t));
     if constexpr (PAIRS)
       rhs_item_pairs<R, K, D, RAIN, MODE>(*ap, t, it_, &sF[0][0], sU, sL, sD, U, auxT, auxS, out, U0, dt_m,
-                                             c0, c1, c2, oT, oS, flags);
+                                          c0, c1, c2, oT, oS, flags);
     else
       rhs_item<R, K, D, RAIN, MODE>(a, it_, sF, sD, U, auxT, auxS, out, U0, dt_m, c0, c1, c2, oT, oS, flags);
     __syncthreads();   // the LDS tiles are reused by the next item
