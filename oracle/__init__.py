@@ -34,7 +34,10 @@ class OraParams(ct.Structure):
 
 class OraMesh(ct.Structure):
     _fields_ = [("dim", ct.c_int), ("n", ct.c_int * 3), ("lo", ct.c_double * 3),
-                ("hi", ct.c_double * 3), ("bc", ct.c_int * 3), ("order", ct.c_int)]
+                ("hi", ct.c_double * 3), ("bc", ct.c_int * 3), ("order", ct.c_int),
+                ("basis", ct.c_int)]
+
+BASES = {"lobatto": 0, "gauss": 1}
 
 
 _lib = None
@@ -49,6 +52,8 @@ def lib():
         dp = ct.POINTER(ct.c_double)
         L.ora_default_params.argtypes = [ct.POINTER(OraParams)]
         L.ora_tables.argtypes = [ct.c_int, dp, dp, dp, dp]
+        L.ora_gauss_tables.argtypes = [ct.c_int, dp, dp]
+        L.ora_project.argtypes = [ct.c_void_p, dp, dp]
         L.ora_esat.argtypes = [ct.POINTER(OraParams), ct.c_double]
         L.ora_esat.restype = ct.c_double
         L.ora_rho_vs.argtypes = [ct.POINTER(OraParams), ct.c_double]
@@ -98,6 +103,14 @@ def tables(k: int):
     return x, w, D, Dh
 
 
+def gauss_tables(k: int):
+    """The (k+1)-point Gauss-Legendre rule of the modal basis: points, weights."""
+    x, w = np.zeros(k + 1), np.zeros(k + 1)
+    if lib().ora_gauss_tables(k, _p(x), _p(w)) != 0:
+        raise ValueError("order out of range")
+    return x, w
+
+
 def esat(P: OraParams, T: float) -> float:
     return lib().ora_esat(ct.byref(P), T)
 
@@ -130,6 +143,7 @@ class Oracle:
             M.n[a] = int(mesh.n[a]); M.lo[a] = float(mesh.lo[a]); M.hi[a] = float(mesh.hi[a])
             M.bc[a] = int(mesh.bc[a])
         M.order = mesh.order
+        M.basis = BASES[getattr(mesh, "basis", "lobatto")]
         self.mesh, self.P, self.nvars = mesh, params, nvars
         self._bg = [np.ascontiguousarray(bg[k], dtype=np.float64) for k in ("rho_d", "rho_m", "rho_r", "E")]
         self.h = lib().ora_create(ct.byref(M), ct.byref(params), nvars, *[_p(a) for a in self._bg])
@@ -217,6 +231,14 @@ class Oracle:
         Fs = np.zeros(self.nvars)
         lib().ora_face(self.h, _p(Um), izm, _p(Up), izp, j, _p(Fs))
         return Fs
+
+    def project(self, U: np.ndarray) -> np.ndarray:
+        """Legendre coefficients of a state given at the Gauss points (modal basis)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        C = np.zeros_like(U)
+        if lib().ora_project(self.h, _p(U), _p(C)) != 0:
+            raise ValueError("projection needs the modal (gauss) basis")
+        return C
 
     def stats(self):
         it, mx, bad = ct.c_long(), ct.c_int(), ct.c_int()

@@ -19,8 +19,16 @@
 //     slip walls ..................................... Section 3.2
 //   * diagonal mass, SSPRK(4,3) ...................... Section 3.3
 //   * pointwise reconstruction ...................... Section 3.4
-// The basis is nodal Gauss-Lobatto collocation on an affine box (nodes double
-// as quadrature points), so the L2 projection of Section 3.4 is the identity.
+// Two spatial bases on an affine box:
+//   * nodal Gauss-Lobatto collocation (nodes double as quadrature points), so
+//     the L2 projection of Section 3.4 is the identity;
+//   * the paper's own: a tensor Legendre (modal) basis of Q^k with its
+//     diagonal mass matrix (Section 3.1) and Gauss-Legendre quadrature with
+//     k+1 points per axis.  The split runs at the quadrature points and T and
+//     rho_v are L2-projected onto Q^k (Section 3.4); face quadrature points
+//     see the traces of these projections.  States cross the interface as
+//     values at the Gauss points and are projected onto the Legendre basis on
+//     entry (and evaluated there on exit).
 //
 // The scalar type is a template parameter: `double` gives the reference
 // values, `Dual` (value + one tangent) gives exact directional derivatives of
@@ -109,6 +117,7 @@ struct OraMesh {
   double lo[3], hi[3];
   int bc[3];        // 0 periodic, 1 slip wall (on both ends of that axis)
   int order;        // polynomial order k
+  int basis;        // 0: Gauss-Lobatto collocation, 1: Legendre modes + Gauss quadrature
 };
 
 void ora_default_params(OraParams* p) {
@@ -194,6 +203,43 @@ Tables make_tables(int k) {
   for (int i = 0; i < p1; ++i)
     for (int a = 0; a < p1; ++a) t.Dhat[i * p1 + a] = t.w[a] * t.D[a * p1 + i] / t.w[i];
   return t;
+}
+
+// P_0..P_k and their derivatives at x by the three-term recurrence
+void legendre_all(int k, double x, double* P, double* dP) {
+  P[0] = 1.0; dP[0] = 0.0;
+  if (k >= 1) { P[1] = x; dP[1] = 1.0; }
+  for (int m = 1; m < k; ++m) {
+    P[m + 1] = ((2.0 * m + 1.0) * x * P[m] - m * P[m - 1]) / (m + 1.0);
+    dP[m + 1] = dP[m - 1] + (2.0 * m + 1.0) * P[m];
+  }
+}
+
+// Gauss-Legendre rule with k+1 points: the roots of P_{k+1} (Newton from the
+// usual cosine guesses) and the weights 2 / ((1 - x^2) P_{k+1}'(x)^2).
+struct Gauss {
+  std::vector<double> x, w;
+};
+
+Gauss make_gauss(int k) {
+  Gauss G;
+  const int p1 = k + 1;
+  G.x.assign(p1, 0.0); G.w.assign(p1, 0.0);
+  for (int i = 0; i < p1; ++i) {
+    double xx = -std::cos(M_PI * (i + 0.75) / (p1 + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double P, dP;
+      legendre(p1, xx, &P, &dP);
+      double dx = P / dP;
+      xx -= dx;
+      if (std::fabs(dx) < 1e-16) break;
+    }
+    double P, dP;
+    legendre(p1, xx, &P, &dP);
+    G.x[i] = xx;
+    G.w[i] = 2.0 / ((1.0 - xx * xx) * dP * dP);
+  }
+  return G;
 }
 
 // ---------------------------------------------------------------------------
@@ -309,6 +355,15 @@ struct Ctx {
   int nvars, np, ne, d, k;
   double h[3];
   std::vector<double> bg_rd, bg_rm, bg_rr, bg_E, bg_p;   // per node height
+  // modal basis (basis = 1): Gauss rule, positions and weights of the nodal
+  // representation, the Legendre basis at the volume quadrature points
+  // (Phi[m*np+q], dPhi[(j*np+m)*np+q] = d/dxi_j), and the split of the
+  // background at the node heights
+  int basis = 0;
+  Gauss gq;
+  std::vector<double> xn, wn;
+  std::vector<double> Phi, dPhi;
+  std::vector<double> bg_T, bg_rv;
   long iters_total = 0;
   int max_iters = 0;
   int bad = 0;
@@ -356,32 +411,29 @@ template <class R> struct Point {
   R lam[3];    // |u_j| + |v_r delta_jz| + c_m
 };
 
-// Pointwise state, split, fluxes (Section 2.3 perturbation form) and sources.
-template <class R> void pointwise(Ctx& c, const R* Uq, int iz, Point<R>& q) {
+// Pointwise state, fluxes (Section 2.3 perturbation form) and sources from the
+// perturbation Uq, the split result (T, rho_v) and the background values
+// (rho_d, rho_m, rho_r, E, p) at the point.
+template <class R> void point_core(const Ctx& c, const R* Uq, R T, R rv, double bgd, double bgm,
+                                   double bgr, double bgE, double bgp, Point<R>& q) {
   const OraParams& P = c.P;
   int d = c.d;
   R rdp = Uq[v_rd()], rmp = Uq[v_rm()];
   R rrp = P.rain ? Uq[v_rr(c)] : R(0.0);
-  q.rd = c.bg_rd[iz] + rdp;
-  q.rm = c.bg_rm[iz] + rmp;
-  q.rr = P.rain ? R(c.bg_rr[iz]) + rrp : R(0.0);
+  q.rd = bgd + rdp;
+  q.rm = bgm + rmp;
+  q.rr = P.rain ? R(bgr) + rrp : R(0.0);
   q.rho = q.rd + q.rm + q.rr;                                   // total density
-  R ke = R(0.0);
   for (int i = 0; i < d; ++i) {
     q.m[i] = Uq[v_m(c, i)];
     q.u[i] = q.m[i] / q.rho;
-    ke += 0.5 * q.m[i] * q.u[i];
   }
-  q.E = c.bg_E[iz] + Uq[v_E(c)];
-  R re = q.E - ke;                                              // rho e = E - rho u.u/2
-  int ok = 1, iters = 0;
-  split(P, q.rd, q.rm, q.rr, re, &q.T, &q.rv, &ok, &iters);
-  c.iters_total += iters;
-  c.max_iters = std::max(c.max_iters, iters);
-  if (!ok) c.bad++;
+  q.E = bgE + Uq[v_E(c)];
+  q.T = T;
+  q.rv = rv;
   q.rc = q.rm - q.rv;
   R p = (q.rd * P.Rd + q.rv * P.Rv) * q.T;                      // equation of state
-  q.pp = p - c.bg_p[iz];
+  q.pp = p - bgp;
   R Cv = P.cvd * q.rd + P.cvv * q.rv + P.cl * (q.rc + q.rr);
   R gam = 1.0 + (q.rd * P.Rd + q.rv * P.Rv) / Cv;               // moist isentropic factor
   q.cm = sqrt(gam * p / q.rho);
@@ -402,7 +454,7 @@ template <class R> void pointwise(Ctx& c, const R* Uq, int iz, Point<R>& q) {
     if (P.rain) q.F[j][v_rr(c)] = q.rr * (q.u[j] - vz);
     for (int i = 0; i < d; ++i)
       q.F[j][v_m(c, i)] = q.m[i] * q.u[j] + (i == j ? q.pp : R(0.0)) - q.rr * vz * q.u[i];
-    q.F[j][v_E(c)] = (q.E + c.bg_p[iz] + q.pp) * q.u[j]
+    q.F[j][v_E(c)] = (q.E + bgp + q.pp) * q.u[j]
                      - (P.cl * (q.T - P.Tref) + 0.5 * u2) * q.rr * vz;
     q.lam[j] = absr(q.u[j]) + absr(vz) + q.cm;
   }
@@ -420,6 +472,31 @@ template <class R> void pointwise(Ctx& c, const R* Uq, int iz, Point<R>& q) {
     q.G[v_rm()] = Sev - Sau - Sac;
     q.G[v_rr(c)] = Sau + Sac - Sev;
   }
+}
+
+// Pointwise reconstruction (Section 3.4): the split of the full state at node
+// height iz, then point_core.
+template <class R> void pointwise(Ctx& c, const R* Uq, int iz, Point<R>& q) {
+  const OraParams& P = c.P;
+  int d = c.d;
+  R rd = c.bg_rd[iz] + Uq[v_rd()];
+  R rm = c.bg_rm[iz] + Uq[v_rm()];
+  R rr = P.rain ? R(c.bg_rr[iz]) + Uq[v_rr(c)] : R(0.0);
+  R rho = rd + rm + rr;
+  R ke = R(0.0);
+  for (int i = 0; i < d; ++i) {
+    R mi = Uq[v_m(c, i)];
+    ke += 0.5 * mi * (mi / rho);
+  }
+  R re = (c.bg_E[iz] + Uq[v_E(c)]) - ke;                        // rho e = E - rho u.u/2
+  int ok = 1, iters = 0;
+  R T, rv;
+  split(P, rd, rm, rr, re, &T, &rv, &ok, &iters);
+  c.iters_total += iters;
+  c.max_iters = std::max(c.max_iters, iters);
+  if (!ok) c.bad++;
+  point_core(c, Uq, T, rv, c.bg_rd[iz], c.bg_rm[iz], P.rain ? c.bg_rr[iz] : 0.0, c.bg_E[iz],
+             c.bg_p[iz], q);
 }
 
 // Lax-Friedrichs flux with normal +e_j: (F(U-) + F(U+)).n / 2 + Lambda/2 (U- - U+)
@@ -540,7 +617,7 @@ double sponge_delta(const Ctx& c, double z) {
 // height of node n of element e
 double node_z(const Ctx& c, int e, int n) {
   const int a = c.d - 1;
-  return c.M.lo[a] + c.h[a] * (elem_axis(c, e, a) + 0.5 * (1.0 + c.tab.x[node_axis(n, a, c.k + 1)]));
+  return c.M.lo[a] + c.h[a] * (elem_axis(c, e, a) + 0.5 * (1.0 + c.xn[node_axis(n, a, c.k + 1)]));
 }
 
 // The sponge at the end of a time step, node by node (with Lobatto
@@ -564,6 +641,266 @@ template <class R> void sponge(Ctx& c, R* U) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// the modal basis (basis = 1)
+// ---------------------------------------------------------------------------
+// ||phi_m||^2 on the reference element: prod_a 2 / (2 m_a + 1)
+double mode_norm(const Ctx& c, int m) {
+  double s = 1.0;
+  for (int a = 0; a < c.d; ++a) s *= 2.0 / (2.0 * node_axis(m, a, c.k + 1) + 1.0);
+  return s;
+}
+
+// product weight of volume quadrature point q
+double quad_w(const Ctx& c, int q) {
+  double w = 1.0;
+  for (int a = 0; a < c.d; ++a) w *= c.gq.w[node_axis(q, a, c.k + 1)];
+  return w;
+}
+
+// every basis function at the reference point xi
+void basis_at(const Ctx& c, const double* xi, double* phi) {
+  double P[3][16], dP[16];
+  for (int a = 0; a < c.d; ++a) legendre_all(c.k, xi[a], P[a], dP);
+  for (int m = 0; m < c.np; ++m) {
+    double v = 1.0;
+    for (int a = 0; a < c.d; ++a) v *= P[a][node_axis(m, a, c.k + 1)];
+    phi[m] = v;
+  }
+}
+
+void make_modal_tables(Ctx& c) {
+  const int np = c.np, d = c.d, p1 = c.k + 1;
+  c.Phi.assign((size_t)np * np, 0.0);
+  c.dPhi.assign((size_t)d * np * np, 0.0);
+  for (int q = 0; q < np; ++q) {
+    double P[3][16], dP[3][16];
+    for (int a = 0; a < d; ++a) legendre_all(c.k, c.gq.x[node_axis(q, a, p1)], P[a], dP[a]);
+    for (int m = 0; m < np; ++m) {
+      double v = 1.0;
+      for (int a = 0; a < d; ++a) v *= P[a][node_axis(m, a, p1)];
+      c.Phi[(size_t)m * np + q] = v;
+      for (int j = 0; j < d; ++j) {
+        double g = 1.0;
+        for (int a = 0; a < d; ++a) {
+          int ma = node_axis(m, a, p1);
+          g *= (a == j) ? dP[a][ma] : P[a][ma];
+        }
+        c.dPhi[((size_t)j * np + m) * np + q] = g;
+      }
+    }
+  }
+}
+
+// L2 projection onto the Legendre modes of values at the volume quadrature
+// points, element by element: c_m = sum_q w_q phi_m(x_q) u_q / ||phi_m||^2
+template <class R> void to_modal(const Ctx& c, int nfields, const R* U, R* C) {
+  const int np = c.np;
+  for (long b = 0; b < (long)nfields * c.ne; ++b)
+    for (int m = 0; m < np; ++m) {
+      R s = R(0.0);
+      for (int q = 0; q < np; ++q) s += (quad_w(c, q) * c.Phi[(size_t)m * np + q]) * U[b * np + q];
+      C[b * np + m] = s / mode_norm(c, m);
+    }
+}
+
+// values at the volume quadrature points: u_q = sum_m c_m phi_m(x_q)
+template <class R> void to_points(const Ctx& c, int nfields, const R* C, R* U) {
+  const int np = c.np;
+  for (long b = 0; b < (long)nfields * c.ne; ++b)
+    for (int q = 0; q < np; ++q) {
+      R s = R(0.0);
+      for (int m = 0; m < np; ++m) s += c.Phi[(size_t)m * np + q] * C[b * np + m];
+      U[b * np + q] = s;
+    }
+}
+
+template <class R> R expand(const Ctx& c, const R* cm, const double* phi) {
+  R s = R(0.0);
+  for (int m = 0; m < c.np; ++m) s += cm[m] * phi[m];
+  return s;
+}
+
+// The background in element row ez at reference height xi_z, as the Legendre
+// expansion (projection onto P^k) of its values at the row's node heights:
+// out = (rho_d, rho_m, rho_r, E, T, rho_v).
+void bg_trace(const Ctx& c, int ez, double xi_z, double* out) {
+  const int p1 = c.k + 1;
+  double P[16], dP[16];
+  legendre_all(c.k, xi_z, P, dP);
+  const std::vector<double>* f[6] = {&c.bg_rd, &c.bg_rm, &c.bg_rr, &c.bg_E, &c.bg_T, &c.bg_rv};
+  for (int i = 0; i < 6; ++i) {
+    double v = 0.0;
+    for (int m = 0; m < p1; ++m) {
+      double beta = 0.0;
+      for (int l = 0; l < p1; ++l) {
+        double Pl[16], dPl[16];
+        legendre_all(c.k, c.gq.x[l], Pl, dPl);
+        beta += c.gq.w[l] * Pl[m] * (*f[i])[ez * p1 + l];
+      }
+      v += (2.0 * m + 1.0) / 2.0 * beta * P[m];
+    }
+    out[i] = v;
+  }
+}
+
+// State at a face quadrature point of element e (reference point xi) from the
+// modal coefficients of U, T and rho_v.  The background pressure there is the
+// equation of state of the traced background, so that an unperturbed state
+// carries no pressure perturbation on faces either.
+template <class R> void face_point(const Ctx& c, const R* C, const R* Tc, const R* Rvc, int e,
+                                   const double* xi, R* Ut, Point<R>& q, double* bgo) {
+  const long N = (long)c.ne * c.np;
+  std::vector<double> phi(c.np);
+  basis_at(c, xi, phi.data());
+  for (int v = 0; v < c.nvars; ++v) Ut[v] = expand(c, C + (long)v * N + (long)e * c.np, phi.data());
+  R T = expand(c, Tc + (long)e * c.np, phi.data());
+  R rv = expand(c, Rvc + (long)e * c.np, phi.data());
+  double b[6];
+  bg_trace(c, elem_axis(c, e, c.d - 1), xi[c.d - 1], b);
+  bgo[0] = b[0]; bgo[1] = b[1]; bgo[2] = c.P.rain ? b[2] : 0.0; bgo[3] = b[3];
+  bgo[4] = (b[0] * c.P.Rd + b[5] * c.P.Rv) * b[4];
+  point_core(c, Ut, T, rv, bgo[0], bgo[1], bgo[2], bgo[3], bgo[4], q);
+}
+
+// slip-wall ghost of a face point: momentum reflected, the traced T, rho_v
+// and background kept
+template <class R> void face_ghost(const Ctx& c, const R* Ut, const Point<R>& qi, const double* bgo, int j,
+                                   R* Ug, Point<R>& qg) {
+  ghost_state(c, Ut, j, Ug);
+  point_core(c, Ug, qi.T, qi.rv, bgo[0], bgo[1], bgo[2], bgo[3], bgo[4], qg);
+}
+
+// dC/dt on the modal coefficients C (Section 3.2 weak form, Section 3.3
+// diagonal mass, Section 3.4 reconstruction):
+//   M dC/dt = (F(U_h), grad phi)_K - <F*, phi>_dK + (G, phi)_K,
+// every integral by the Gauss rule of k+1 points per axis.
+template <class R> void modal_rhs(Ctx& c, const R* C, R* dC, double* wall_rain_flux) {
+  const int nv = c.nvars, np = c.np, ne = c.ne, d = c.d, k = c.k, p1 = k + 1;
+  const long N = (long)ne * np;
+  auto at = [&](int v, int e, int n) -> long { return (long)v * N + (long)e * np + n; };
+  // 1. the state at the volume quadrature points, its split, fluxes and sources
+  std::vector<R> Uq((size_t)nv * N);
+  to_points(c, nv, C, Uq.data());
+  std::vector<Point<R>> q(N);
+  std::vector<R> Tq(N), Rvq(N), u(nv);
+  for (int e = 0; e < ne; ++e)
+    for (int n = 0; n < np; ++n) {
+      for (int v = 0; v < nv; ++v) u[v] = Uq[at(v, e, n)];
+      Point<R>& qq = q[(long)e * np + n];
+      pointwise(c, u.data(), height_of(c, e, n), qq);
+      Tq[(long)e * np + n] = qq.T;
+      Rvq[(long)e * np + n] = qq.rv;
+    }
+  // 2. L2 projections of T and rho_v onto Q^k
+  std::vector<R> Tc(N), Rvc(N);
+  to_modal(c, 1, Tq.data(), Tc.data());
+  to_modal(c, 1, Rvq.data(), Rvc.data());
+  // 3. volume and source integrals
+  for (int e = 0; e < ne; ++e)
+    for (int m = 0; m < np; ++m)
+      for (int v = 0; v < nv; ++v) {
+        R acc = R(0.0);
+        for (int n = 0; n < np; ++n) {
+          const Point<R>& qq = q[(long)e * np + n];
+          const double w = quad_w(c, n);
+          for (int j = 0; j < d; ++j)
+            acc += (w * (2.0 / c.h[j]) * c.dPhi[((size_t)j * np + m) * np + n]) * qq.F[j][v];
+          acc += (w * c.Phi[(size_t)m * np + n]) * qq.G[v];
+        }
+        dC[at(v, e, m)] = acc;
+      }
+  // 4. faces with normal +e_j, Gauss points on the face
+  int nf = 1;
+  for (int a = 0; a < d - 1; ++a) nf *= p1;
+  std::vector<R> Um(nv), Up(nv), Ug(nv), Fs(nv);
+  std::vector<double> phiM(np), phiP(np);
+  double wflux = 0.0;
+  for (int j = 0; j < d; ++j) {
+    const bool wall = c.M.bc[j] == 1;
+    for (int e = 0; e < ne; ++e) {
+      const int ej = elem_axis(c, e, j);
+      const bool top = ej == c.M.n[j] - 1, bottom = ej == 0;
+      for (int f = 0; f < nf; ++f) {
+        double xi[3], wf = 1.0, wphys = 1.0;
+        int o = f;
+        for (int a = 0; a < d; ++a) {
+          if (a == j) continue;
+          int ia = o % p1;
+          o /= p1;
+          xi[a] = c.gq.x[ia];
+          wf *= c.gq.w[ia];
+          wphys *= c.gq.w[ia] * 0.5 * c.h[a];
+        }
+        const double lift = 2.0 / c.h[j];
+        // plus face of e (xi_j = +1)
+        xi[j] = 1.0;
+        basis_at(c, xi, phiM.data());
+        Point<R> qm, qp;
+        double bm[5], bp[5];
+        face_point(c, C, Tc.data(), Rvc.data(), e, xi, Um.data(), qm, bm);
+        if (wall && top) {
+          Point<R> qg;
+          face_ghost(c, Um.data(), qm, bm, j, Ug.data(), qg);
+          lf_flux(c, qm, Um.data(), qg, Ug.data(), j, Fs.data());
+          for (int m = 0; m < np; ++m)
+            for (int v = 0; v < nv; ++v) dC[at(v, e, m)] -= (lift * wf * phiM[m]) * Fs[v];
+          if (c.P.rain) wflux += wphys * val(Fs[v_rr(c)]);
+        } else {
+          const int e2 = elem_shift(c, e, j, +1);
+          xi[j] = -1.0;
+          basis_at(c, xi, phiP.data());
+          face_point(c, C, Tc.data(), Rvc.data(), e2, xi, Up.data(), qp, bp);
+          lf_flux(c, qm, Um.data(), qp, Up.data(), j, Fs.data());
+          for (int m = 0; m < np; ++m)
+            for (int v = 0; v < nv; ++v) {
+              dC[at(v, e, m)] -= (lift * wf * phiM[m]) * Fs[v];
+              dC[at(v, e2, m)] += (lift * wf * phiP[m]) * Fs[v];
+            }
+        }
+        if (wall && bottom) {
+          // minus face of e (xi_j = -1) on the wall: the ghost is the minus side
+          xi[j] = -1.0;
+          basis_at(c, xi, phiP.data());
+          Point<R> qi, qg;
+          face_point(c, C, Tc.data(), Rvc.data(), e, xi, Up.data(), qi, bp);
+          face_ghost(c, Up.data(), qi, bp, j, Ug.data(), qg);
+          lf_flux(c, qg, Ug.data(), qi, Up.data(), j, Fs.data());
+          for (int m = 0; m < np; ++m)
+            for (int v = 0; v < nv; ++v) dC[at(v, e, m)] += (lift * wf * phiP[m]) * Fs[v];
+          if (c.P.rain) wflux -= wphys * val(Fs[v_rr(c)]);
+        }
+      }
+    }
+  }
+  // 5. inverse of the diagonal mass matrix (J cancels against the 2/h factors)
+  for (int v = 0; v < nv; ++v)
+    for (int e = 0; e < ne; ++e)
+      for (int m = 0; m < np; ++m) dC[at(v, e, m)] = dC[at(v, e, m)] / mode_norm(c, m);
+  if (wall_rain_flux) *wall_rain_flux = wflux;
+}
+
+// The sponge on modal coefficients: the pointwise update at the volume
+// quadrature points, then the L2 projection back onto Q^k (Section 3.6).
+template <class R> void sponge_modal(Ctx& c, R* C) {
+  if (!(c.P.sponge_alpha > 0.0)) return;
+  const long n = (long)c.nvars * c.ne * c.np;
+  std::vector<R> U(n);
+  to_points(c, c.nvars, C, U.data());
+  sponge(c, U.data());
+  to_modal(c, c.nvars, U.data(), C);
+}
+
+template <class R> void any_rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
+  if (c.basis == 1) modal_rhs(c, U, dU, wall_rain_flux);
+  else rhs(c, U, dU, wall_rain_flux);
+}
+
+template <class R> void any_sponge(Ctx& c, R* U) {
+  if (c.basis == 1) sponge_modal(c, U);
+  else sponge(c, U);
+}
+
 // SSP Runge-Kutta step in Shu-Osher form (Section 3.3 remark): SSPRK(4,3) of
 // Kraaijevanger, or the three-stage SSPRK(3,3); the sponge, when on, closes
 // the step.
@@ -574,25 +911,25 @@ template <class R> void rk_step(Ctx& c, R* U, double dt, int scheme, double* out
   if (scheme == 0) {
     // u1 = u0 + dt/2 L(u0); u2 = u1 + dt/2 L(u1);
     // u3 = 2/3 u0 + 1/3 u2 + dt/6 L(u2); u4 = u3 + dt/2 L(u3)
-    rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
     for (long i = 0; i < N; ++i) us[i] = u0[i] + (0.5 * dt) * L[i];
-    rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
     for (long i = 0; i < N; ++i) us[i] = us[i] + (0.5 * dt) * L[i];
-    rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
     for (long i = 0; i < N; ++i) us[i] = (2.0 / 3.0) * u0[i] + (1.0 / 3.0) * us[i] + (dt / 6.0) * L[i];
-    rhs(c, us.data(), L.data(), &f); fl += f / 2.0;
+    any_rhs(c, us.data(), L.data(), &f); fl += f / 2.0;
     for (long i = 0; i < N; ++i) U[i] = us[i] + (0.5 * dt) * L[i];
   } else {
     // u1 = u0 + dt L(u0); u2 = 3/4 u0 + 1/4 u1 + dt/4 L(u1);
     // u3 = 1/3 u0 + 2/3 u2 + 2/3 dt L(u2)
-    rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
     for (long i = 0; i < N; ++i) us[i] = u0[i] + dt * L[i];
-    rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
     for (long i = 0; i < N; ++i) us[i] = 0.75 * u0[i] + 0.25 * us[i] + (0.25 * dt) * L[i];
-    rhs(c, us.data(), L.data(), &f); fl += f * (2.0 / 3.0);
+    any_rhs(c, us.data(), L.data(), &f); fl += f * (2.0 / 3.0);
     for (long i = 0; i < N; ++i) U[i] = (1.0 / 3.0) * u0[i] + (2.0 / 3.0) * us[i] + ((2.0 / 3.0) * dt) * L[i];
   }
-  sponge(c, U);
+  any_sponge(c, U);
   if (outflow) *outflow = fl * dt;
 }
 
@@ -643,6 +980,7 @@ int ora_split_jvp(const OraParams* P, double rd, double rm, double rr, double re
 void* ora_create(const OraMesh* M, const OraParams* P, int nvars, const double* rd,
                  const double* rm, const double* rr, const double* E) {
   if (M->dim < 2 || M->dim > 3 || M->order < 1 || M->order > 8) return nullptr;
+  if (M->basis != 0 && M->basis != 1) return nullptr;
   if (nvars != (P->rain ? 4 : 3) + M->dim) return nullptr;
   Ctx* c = new Ctx();
   c->M = *M; c->P = *P;
@@ -658,12 +996,35 @@ void* ora_create(const OraMesh* M, const OraParams* P, int nvars, const double* 
   c->bg_rd.assign(rd, rd + nzq); c->bg_rm.assign(rm, rm + nzq);
   c->bg_rr.assign(rr, rr + nzq); c->bg_E.assign(E, E + nzq);
   c->bg_p.assign(nzq, 0.0);
+  c->bg_T.assign(nzq, 0.0);
+  c->bg_rv.assign(nzq, 0.0);
   for (int iz = 0; iz < nzq; ++iz) {
     double rrr = P->rain ? rr[iz] : 0.0;
     SplitOut s = split_double(*P, rd[iz], rm[iz], rrr, E[iz]);
     c->bg_p[iz] = (rd[iz] * P->Rd + s.rv * P->Rv) * s.T;
+    c->bg_T[iz] = s.T;
+    c->bg_rv[iz] = s.rv;
+  }
+  c->basis = M->basis;
+  if (c->basis == 1) {
+    c->gq = make_gauss(c->k);
+    c->xn = c->gq.x;
+    c->wn = c->gq.w;
+    make_modal_tables(*c);
+  } else {
+    c->xn = c->tab.x;
+    c->wn = c->tab.w;
   }
   return c;
+}
+
+// Gauss-Legendre rule of k+1 points
+int ora_gauss_tables(int k, double* x, double* w) {
+  if (k < 0 || k > 12) return -1;
+  Gauss G = make_gauss(k);
+  std::memcpy(x, G.x.data(), (k + 1) * sizeof(double));
+  std::memcpy(w, G.w.data(), (k + 1) * sizeof(double));
+  return 0;
 }
 
 void ora_destroy(void* h) { delete (Ctx*)h; }
@@ -695,10 +1056,47 @@ int ora_split_field(void* h, const double* U, double* T, double* rv, double* rc,
   return c->bad - bad;
 }
 
+}  // extern "C"
+
+namespace {
+// right-hand side of a state given by its node values (Gauss points for the
+// modal basis: projected on entry, the result evaluated there on exit)
+template <class R> void nodal_rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
+  if (c.basis == 0) { rhs(c, U, dU, wall_rain_flux); return; }
+  const long n = (long)c.nvars * c.ne * c.np;
+  std::vector<R> C(n), dC(n);
+  to_modal(c, c.nvars, U, C.data());
+  modal_rhs(c, C.data(), dC.data(), wall_rain_flux);
+  to_points(c, c.nvars, dC.data(), dU);
+}
+
+// nsteps RK steps of a nodal state in place
+template <class R> void nodal_rk(Ctx& c, R* U, double dt, int nsteps, int scheme, double* outflow) {
+  const long n = (long)c.nvars * c.ne * c.np;
+  std::vector<R> C;
+  R* X = U;
+  if (c.basis == 1) {
+    C.resize(n);
+    to_modal(c, c.nvars, U, C.data());
+    X = C.data();
+  }
+  double acc = 0.0;
+  for (int s = 0; s < nsteps; ++s) {
+    double f = 0.0;
+    rk_step(c, X, dt, scheme, outflow ? &f : nullptr);
+    acc += f;
+  }
+  if (c.basis == 1) to_points(c, c.nvars, C.data(), U);
+  if (outflow) *outflow = acc;
+}
+}  // namespace
+
+extern "C" {
+
 int ora_rhs(void* h, const double* U, double* dU, double* wall_rain_flux) {
   Ctx* c = (Ctx*)h;
   int bad = c->bad;
-  rhs(*c, U, dU, wall_rain_flux);
+  nodal_rhs(*c, U, dU, wall_rain_flux);
   return c->bad - bad;
 }
 
@@ -708,11 +1106,7 @@ int ora_rk_step(void* h, double* U, double dt, int nsteps, int scheme, double* o
   Ctx* c = (Ctx*)h;
   int bad = c->bad;
   double acc = 0.0;
-  for (int s = 0; s < nsteps; ++s) {
-    double f = 0.0;
-    rk_step(*c, U, dt, scheme, &f);
-    acc += f;
-  }
+  nodal_rk(*c, U, dt, nsteps, scheme, &acc);
   if (outflow) *outflow = acc;
   return c->bad - bad;
 }
@@ -724,7 +1118,7 @@ int ora_rhs_jvp(void* h, const double* U, const double* V, double* dU, double* J
   std::vector<Dual> Ud(N), Rd(N);
   for (long i = 0; i < N; ++i) Ud[i] = Dual(U[i], V[i]);
   int bad = c->bad;
-  rhs(*c, Ud.data(), Rd.data(), nullptr);
+  nodal_rhs(*c, Ud.data(), Rd.data(), nullptr);
   for (long i = 0; i < N; ++i) { if (dU) dU[i] = Rd[i].v; JV[i] = Rd[i].d; }
   return c->bad - bad;
 }
@@ -736,14 +1130,22 @@ int ora_rk_jvp(void* h, double* U, double* V, double dt, int nsteps, int scheme)
   std::vector<Dual> Ud(N);
   for (long i = 0; i < N; ++i) Ud[i] = Dual(U[i], V[i]);
   int bad = c->bad;
-  for (int s = 0; s < nsteps; ++s) rk_step(*c, Ud.data(), dt, scheme, nullptr);
+  nodal_rk(*c, Ud.data(), dt, nsteps, scheme, nullptr);
   for (long i = 0; i < N; ++i) { U[i] = Ud[i].v; V[i] = Ud[i].d; }
   return c->bad - bad;
 }
 
 // sponge blending function at height z, and the sponge applied once to U
 double ora_sponge_delta(void* h, double z) { return sponge_delta(*(Ctx*)h, z); }
-void ora_sponge_apply(void* h, double* U) { sponge(*(Ctx*)h, U); }
+void ora_sponge_apply(void* h, double* U) {
+  Ctx* c = (Ctx*)h;
+  if (c->basis == 0) { sponge(*c, U); return; }
+  const long n = (long)c->nvars * c->ne * c->np;
+  std::vector<double> C(n);
+  to_modal(*c, c->nvars, U, C.data());
+  sponge_modal(*c, C.data());
+  to_points(*c, c->nvars, C.data(), U);
+}
 
 // M_d = sum w J rho_d', M_w = sum w J (rho_m' + rho_r'), and the instantaneous
 // rain mass flux out through the walls
@@ -757,7 +1159,7 @@ void ora_mass(void* h, const double* U, double* out3) {
   for (int e = 0; e < c->ne; ++e)
     for (int n = 0; n < c->np; ++n) {
       double w = J;
-      for (int a = 0; a < c->d; ++a) w *= c->tab.w[node_axis(n, a, p1)];
+      for (int a = 0; a < c->d; ++a) w *= c->wn[node_axis(n, a, p1)];
       long i = (long)e * c->np + n;
       md += w * U[i];
       mw += w * (U[N + i] + (c->P.rain ? U[2 * N + i] : 0.0));
@@ -765,7 +1167,7 @@ void ora_mass(void* h, const double* U, double* out3) {
   out3[0] = md; out3[1] = mw;
   std::vector<double> dU(N * c->nvars);
   double f = 0.0;
-  rhs(*c, U, dU.data(), &f);
+  nodal_rhs(*c, U, dU.data(), &f);
   out3[2] = f;
 }
 
@@ -790,6 +1192,15 @@ void ora_face(void* h, const double* Um, int izm, const double* Up, int izp, int
   pointwise(*c, Um, izm, a);
   pointwise(*c, Up, izp, b);
   lf_flux(*c, a, Um, b, Up, j, Fs);
+}
+
+// Legendre coefficients (the L2 projection by the Gauss rule) of a state given
+// at the Gauss points; modal basis only
+int ora_project(void* h, const double* U, double* C) {
+  Ctx* c = (Ctx*)h;
+  if (c->basis != 1) return -1;
+  to_modal(*c, c->nvars, U, C);
+  return 0;
 }
 
 void ora_stats(void* h, long* iters_total, int* max_iters, int* bad) {

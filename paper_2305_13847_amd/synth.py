@@ -45,6 +45,10 @@ class Mesh:
     hi: Sequence[float]
     bc: Sequence[int]
     order: int
+    # "lobatto": nodes at the Gauss-Lobatto points (collocation); "gauss":
+    # nodes at the Gauss-Legendre points (the paper's modal Legendre space
+    # with Gauss quadrature, held by its values at the quadrature points)
+    basis: str = "lobatto"
 
     @property
     def ne(self) -> int:
@@ -91,6 +95,10 @@ class Case:
 # ----------------------------------------------------------------------------
 # geometry
 # ----------------------------------------------------------------------------
+def _sfx(basis: str) -> str:
+    return "" if basis == "lobatto" else "-" + basis
+
+
 def lobatto_points(k: int) -> np.ndarray:
     """Gauss-Lobatto points on [-1, 1]: +-1 and the roots of P_k' (numpy)."""
     from numpy.polynomial import legendre as L
@@ -102,10 +110,24 @@ def lobatto_points(k: int) -> np.ndarray:
     return np.concatenate([[-1.0], inner, [1.0]])
 
 
+def gauss_points(k: int) -> np.ndarray:
+    """The k + 1 Gauss-Legendre points on [-1, 1] (numpy)."""
+    return np.polynomial.legendre.leggauss(k + 1)[0]
+
+
+def mesh_points(mesh: Mesh) -> np.ndarray:
+    """Reference node positions of the mesh's basis."""
+    if mesh.basis == "gauss":
+        return gauss_points(mesh.order)
+    if mesh.basis != "lobatto":
+        raise ValueError("unknown basis %r" % (mesh.basis,))
+    return lobatto_points(mesh.order)
+
+
 def node_coords(mesh: Mesh) -> List[np.ndarray]:
     """Physical coordinates of every node, one (ne, npe) array per axis."""
     k, d = mesh.order, mesh.dim
-    xi = lobatto_points(k)
+    xi = mesh_points(mesh)
     p1 = k + 1
     # element multi-index (x fastest) and node multi-index (i fastest)
     e_idx = np.unravel_index(np.arange(mesh.ne), tuple(reversed(mesh.n)))
@@ -122,7 +144,7 @@ def node_coords(mesh: Mesh) -> List[np.ndarray]:
 
 def node_heights(mesh: Mesh) -> np.ndarray:
     """Height of every vertical node index iz = ez*(k+1) + l."""
-    xi = lobatto_points(mesh.order)
+    xi = mesh_points(mesh)
     hz = mesh.h[-1]
     ez = np.arange(mesh.n[-1])
     z = mesh.lo[-1] + (ez[:, None] + 0.5 * (xi[None, :] + 1.0)) * hz
@@ -288,7 +310,7 @@ def _modes(rng, X, L, nmodes=3):
 
 
 def periodic_smooth(n=(16, 16), order=2, seed=1, nsteps=10, sat_fraction=0.3,
-                    dim=2) -> Case:
+                    dim=2, basis="lobatto") -> Case:
     """Smooth periodic moist fields on the unit square (or cube), g = 0.
 
     Densities vary by 1%, the moist mixing ratio spans 2-20 g/kg, the velocity
@@ -297,7 +319,7 @@ def periodic_smooth(n=(16, 16), order=2, seed=1, nsteps=10, sat_fraction=0.3,
     split (by the Magnus estimate).
     """
     rng = np.random.default_rng(seed)
-    mesh = Mesh(dim, list(n), [0.0] * dim, [1.0] * dim, [PERIODIC] * dim, order)
+    mesh = Mesh(dim, list(n), [0.0] * dim, [1.0] * dim, [PERIODIC] * dim, order, basis)
     X = node_coords(mesh)
     Ls = [1.0] * dim
     s_d, s_q, s_T = (_modes(rng, X, Ls) for _ in range(3))
@@ -329,20 +351,20 @@ def periodic_smooth(n=(16, 16), order=2, seed=1, nsteps=10, sat_fraction=0.3,
     U = _layout([rd - bg["rho_d"][0], rm - bg["rho_m"][0]] + m + [E - bg["E"][0]])
     umax = float(np.max(np.sqrt(sum(ua * ua for ua in u))))
     dt = cfl_dt(mesh, umax, 0.0, 0.2)
-    return Case("periodic-%dd-q%d-%s" % (dim, order, "x".join(map(str, n))), mesh, 3 + dim, 0,
+    return Case("periodic-%dd-q%d-%s%s" % (dim, order, "x".join(map(str, n)), _sfx(basis)), mesh, 3 + dim, 0,
                 0.0, 0.0, bg, U, dt, nsteps, seed,
                 info=dict(T0=T0, sat_fraction_magnus=frac_sat(T0)))
 
 
 def moist_bubble(n=(128, 64), order=4, seed=2, nsteps=1000, amp=2.0, centre=(10e3, 2e3),
-                 radius=2e3, noise=1e-4, ratio=1.3, Ts=300.0, top=10e3) -> Case:
+                 radius=2e3, noise=1e-4, ratio=1.3, Ts=300.0, top=10e3, basis="lobatto") -> Case:
     """2D moist rising bubble in a cloudy background (Bryan-Fritsch shape).
 
     Domain 20 km x `top` (10 km), periodic in x, slip walls in z, gravity on,
     no rain.
     """
     rng = np.random.default_rng(seed)
-    mesh = Mesh(2, list(n), [0.0, 0.0], [20e3, top], [PERIODIC, WALL], order)
+    mesh = Mesh(2, list(n), [0.0, 0.0], [20e3, top], [PERIODIC, WALL], order, basis)
     bgf = background(mesh, Ts, lambda z: ratio + 0.0 * z)
     X = node_coords(mesh)
     th = bubble(X, centre, radius, amp)
@@ -351,12 +373,12 @@ def moist_bubble(n=(128, 64), order=4, seed=2, nsteps=1000, amp=2.0, centre=(10e
         add_noise(rng, U, mesh, _bg_at_nodes(mesh, bgf), rain=False, level=noise)
     dt = cfl_dt(mesh, 5.0, 0.0, 0.2)
     bg = {k: bgf[k] for k in ("rho_d", "rho_m", "rho_r", "E")}
-    return Case("bubble-2d-q%d-%dx%d" % (order, n[0], n[1]), mesh, 5, 0, C["g"], 0.0, bg, U, dt,
+    return Case("bubble-2d-q%d-%dx%d%s" % (order, n[0], n[1], _sfx(basis)), mesh, 5, 0, C["g"], 0.0, bg, U, dt,
                 nsteps, seed, bg_full=bgf)
 
 
 def warm_rain_3d(n=(64, 64, 32), order=3, seed=3, nsteps=500, nbubbles=8, noise=1e-4,
-                 vr=5.0) -> Case:
+                 vr=5.0, basis="lobatto") -> Case:
     """3D warm-rain thermals: Kessler on, rain falling at a constant 5 m/s.
 
     Domain 20 x 20 x 10 km, periodic in x and y, slip walls in z.  The background
@@ -364,7 +386,7 @@ def warm_rain_3d(n=(64, 64, 32), order=3, seed=3, nsteps=500, nbubbles=8, noise=
     positions and a Gaussian rain blob 1 km above each.
     """
     rng = np.random.default_rng(seed)
-    mesh = Mesh(3, list(n), [0.0, 0.0, 0.0], [20e3, 20e3, 10e3], [PERIODIC, PERIODIC, WALL], order)
+    mesh = Mesh(3, list(n), [0.0, 0.0, 0.0], [20e3, 20e3, 10e3], [PERIODIC, PERIODIC, WALL], order, basis)
     bgf = background(mesh, 300.0, lambda z: 0.8 + 0.25 * (1.0 + np.tanh((z - 1500.0) / 300.0)))
     X = node_coords(mesh)
     th = np.zeros_like(X[0])
@@ -381,7 +403,7 @@ def warm_rain_3d(n=(64, 64, 32), order=3, seed=3, nsteps=500, nbubbles=8, noise=
         add_noise(rng, U, mesh, _bg_at_nodes(mesh, bgf), rain=True, level=noise)
     dt = cfl_dt(mesh, 5.0, vr, 0.2)
     bg = {k: bgf[k] for k in ("rho_d", "rho_m", "rho_r", "E")}
-    return Case("rain-3d-q%d-%dx%dx%d" % (order, *n), mesh, 7, 1, C["g"], vr, bg, U, dt, nsteps, seed,
+    return Case("rain-3d-q%d-%dx%dx%d%s" % (order, *n, _sfx(basis)), mesh, 7, 1, C["g"], vr, bg, U, dt, nsteps, seed,
                 bg_full=bgf)
 
 
@@ -424,7 +446,8 @@ def _T_of_theta_e(th, p, qw, lo=180.0, hi=340.0, iters=80):
 
 
 def gravity_waves(n=(300, 10), order=3, t_end=3600.0, dtheta=0.01, u0=20.0, qw=0.02, N2=1.0e-4,
-                  theta0=300.0, a=5.0e3, cfl=0.5, length=300.0e3, height=10.0e3, periodic=True) -> Case:
+                  theta0=300.0, a=5.0e3, cfl=0.5, length=300.0e3, height=10.0e3, periodic=True,
+                  basis="lobatto") -> Case:
     """Inertia gravity waves in a saturated atmosphere (Section 4.1; set-up of
     Appendix B.1).
 
@@ -444,7 +467,7 @@ def gravity_waves(n=(300, 10), order=3, t_end=3600.0, dtheta=0.01, u0=20.0, qw=0
     """
     from scipy.integrate import solve_ivp
     g = C["g"]
-    mesh = Mesh(2, list(n), [0.0, 0.0], [length, height], [PERIODIC, WALL], order)
+    mesh = Mesh(2, list(n), [0.0, 0.0], [length, height], [PERIODIC, WALL], order, basis)
     z = node_heights(mesh)
 
     def the(zz):
@@ -483,7 +506,7 @@ def gravity_waves(n=(300, 10), order=3, t_end=3600.0, dtheta=0.01, u0=20.0, qw=0
     dt = cfl_dt(mesh, u0, 0.0, cfl)
     nsteps = int(np.ceil(t_end / dt))
     bg = {k: bgf[k] for k in ("rho_d", "rho_m", "rho_r", "E")}
-    return Case("gravity-waves-q%d-%dx%d" % (order, *n), mesh, 5, 0, g, 0.0, bg, U, t_end / nsteps, nsteps, 0,
+    return Case("gravity-waves-q%d-%dx%d%s" % (order, *n, _sfx(basis)), mesh, 5, 0, g, 0.0, bg, U, t_end / nsteps, nsteps, 0,
                 info=dict(t_end=t_end, qw=qw, N2=N2, u0=u0), bg_full=bgf)
 
 

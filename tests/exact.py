@@ -34,9 +34,16 @@ def conservative(mesh, rd, rv, rc, rr, T, u, bg=None, rain=False):
     return np.ascontiguousarray(np.stack(fl)), bg
 
 
-def periodic_mesh(n, order, L=1.0, dim=2, lo=None):
+def periodic_mesh(n, order, L=1.0, dim=2, lo=None, basis="lobatto"):
     lo = [0.0] * dim if lo is None else lo
-    return synth.Mesh(dim, list(n), list(lo), [lo[a] + L for a in range(dim)], [0] * dim, order)
+    return synth.Mesh(dim, list(n), list(lo), [lo[a] + L for a in range(dim)], [0] * dim, order, basis)
+
+
+def _weights_1d(mesh):
+    """Quadrature weights of the mesh's nodes: Lobatto, or Gauss for the modal basis."""
+    if getattr(mesh, "basis", "lobatto") == "gauss":
+        return O.gauss_tables(mesh.order)[1]
+    return O.tables(mesh.order)[1]
 
 
 def vortex(mesh, t, u0=(1.0, 0.5), beta=2.0, rho_inf=1.0, p_inf=1e5, r0=None):
@@ -88,8 +95,8 @@ def moist_contact(mesh, t, u0=(20.0, 10.0), p=8e4, Tm=285.0, dT=4.0, cloud=3e-3)
 
 
 def l2(mesh, f):
-    """Discrete L2 norm with the Lobatto weights and the element Jacobian."""
-    x, w, _, _ = O.tables(mesh.order)
+    """Discrete L2 norm with the nodes' quadrature weights and the element Jacobian."""
+    w = _weights_1d(mesh)
     p1 = mesh.order + 1
     W = np.ones(p1 ** mesh.dim)
     for a in range(mesh.dim):
@@ -100,7 +107,7 @@ def l2(mesh, f):
 
 
 def node_weights(mesh):
-    x, w, _, _ = O.tables(mesh.order)
+    w = _weights_1d(mesh)
     p1 = mesh.order + 1
     W = np.ones(p1 ** mesh.dim)
     for a in range(mesh.dim):

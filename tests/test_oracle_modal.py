@@ -1,0 +1,157 @@
+"""Pins of the reference's modal variant: the paper's own spatial basis, a tensor
+Legendre basis of Q^k with its diagonal mass matrix (Section 3.1) and
+Gauss-Legendre quadrature of k+1 points per axis, with the split at the
+quadrature points and the L2 projection of T and rho_v (Section 3.4).
+
+- The Gauss rule is numpy's, and the projection of a Legendre product returns
+  that single mode (the definition of the basis).
+- A uniform moving state and the hydrostatic rest state are steady.
+- Exact solutions converge at order k+1: a saturated cloudy contact and the
+  dry isentropic vortex.
+- With slip walls, gravity and rain, the dry mass is conserved and the water
+  mass changes by the rain that left through the floor.
+- A 3D state constant in y gives the 2D right-hand side.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2305_13847_amd import synth
+from exact import conservative, l2, moist_contact, node_weights, periodic_mesh, vortex
+
+
+def test_gauss_rule_is_numpys():
+    for k in range(1, 7):
+        x, w = O.gauss_tables(k)
+        X, W = np.polynomial.legendre.leggauss(k + 1)
+        np.testing.assert_allclose(x, X, rtol=0, atol=2e-15)
+        np.testing.assert_allclose(w, W, rtol=0, atol=2e-15)
+
+
+def test_projection_of_a_legendre_product_is_that_mode():
+    k = 3
+    mesh = periodic_mesh((2, 3), k, L=100.0, basis="gauss")
+    p1 = k + 1
+    xg = synth.gauss_points(k)
+    i = np.arange(p1 ** 2) % p1
+    j = np.arange(p1 ** 2) // p1
+    P = lambda m, x: np.polynomial.legendre.legval(x, [0] * m + [1])
+    modes = [(0, 0), (1, 0), (2, 1), (3, 3), (0, 2)]
+    U = np.stack([np.broadcast_to(P(a, xg[i]) * P(b, xg[j]), (mesh.ne, p1 ** 2)) for a, b in modes])
+    bg = dict(rho_d=np.ones(mesh.nzq), rho_m=np.full(mesh.nzq, 0.01), rho_r=np.zeros(mesh.nzq),
+              E=np.full(mesh.nzq, 2.0e5))
+    o = O.Oracle(mesh, O.default_params(g=0.0), 5, bg)
+    C = o.project(U)
+    for v, (a, b) in enumerate(modes):
+        want = np.zeros(p1 ** 2)
+        want[a + p1 * b] = 1.0
+        np.testing.assert_allclose(C[v], np.broadcast_to(want, C[v].shape), rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_uniform_moving_state_is_steady(k):
+    mesh = periodic_mesh((3, 4), k, L=1000.0, basis="gauss")
+    one = np.ones((mesh.ne, mesh.npe))
+    T = 283.0
+    rvs = float(O.rho_vs(O.default_params(), T))
+    U, bg = conservative(mesh, 1.1 * one, rvs * one, 2e-3 * one, 0 * one, T * one, [12.0 * one, -7.0 * one])
+    o = O.Oracle(mesh, O.default_params(g=0.0), 5, bg)
+    R = o.rhs(U)
+    # scale: the momentum flux over an element, rho u^2 / h
+    assert np.abs(R).max() < 1e-12 * 1.1 * 12.0 ** 2 / mesh.h[0] * 1e3
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_hydrostatic_rest_state_is_steady(k):
+    c = synth.moist_bubble(n=(4, 5), order=k, noise=0.0, amp=0.0, basis="gauss")
+    o = O.Oracle.for_case(c)
+    R = o.rhs(np.zeros_like(c.U))
+    # against the gravity term rho g of the background
+    scale = 9.81 * c.bg["rho_d"].max()
+    assert np.abs(R).max() < 1e-12 * scale, np.abs(R).max(axis=(1, 2))
+
+
+def _run(f, k, n, tend, umax, L=10.0, cfl=0.2):
+    mesh = periodic_mesh((n, n), k, L=L, basis="gauss")
+    P = O.default_params(g=0.0)
+    U0, bg = conservative(mesh, *f(mesh, 0.0))
+    Ue, _ = conservative(mesh, *f(mesh, tend), bg=bg)
+    o = O.Oracle(mesh, P, 5, bg)
+    dt0 = cfl * mesh.h[0] / ((2 * k + 1) * umax)
+    ns = int(np.ceil(tend / dt0))
+    U1, _ = o.rk(U0, tend / ns, ns)
+    return max(l2(mesh, U1[v] - Ue[v]) / l2(mesh, Ue[v]) for v in range(5) if l2(mesh, Ue[v]) > 0)
+
+
+@pytest.mark.parametrize("k,ns,min_rate", [(1, (8, 16), 1.8), (2, (8, 16), 2.5), (3, (4, 8), 3.6)])
+def test_moist_contact_order(k, ns, min_rate):
+    f = lambda m, t: moist_contact(m, t, u0=(1000.0, 500.0))
+    e = [_run(f, k, n, 0.25 * 10.0 / 1118.0, 1118.0 + 360.0) for n in ns]
+    rate = np.log2(e[-2] / e[-1])
+    assert rate > min_rate, (e, rate)
+
+
+def test_vortex_order_q3():
+    f = lambda m, t: vortex(m, t, u0=(2.0, 1.0), r0=1.0)
+    tend = 0.25 * 10.0 / (2.24 * 316.0)
+    e = [_run(f, 3, n, tend, 2.5 * 316 + 330) for n in (8, 16)]
+    rate = np.log2(e[0] / e[1])
+    assert e[-1] < 2e-3 and rate > 3.3, (e, rate)
+
+
+def test_rain_mass_budget_with_walls():
+    c = synth.warm_rain_3d(n=(3, 3, 4), order=2, basis="gauss")
+    o = O.Oracle.for_case(c)
+    m0 = o.mass(c.U)
+    U1, out = o.rk(c.U, c.dt, 3)
+    m1 = o.mass(U1)
+    W = node_weights(c.mesh)
+    scale = np.sum(W * c.bg["rho_m"][synth.height_index(c.mesh)])
+    assert abs(m1[0] - m0[0]) < 1e-12 * scale
+    assert out > 0.0
+    assert abs((m1[1] - m0[1]) + out) < 1e-10 * scale, (m1[1] - m0[1], out)
+
+
+def test_3d_constant_in_y_gives_2d():
+    k = 2
+    c2 = synth.moist_bubble(n=(4, 3), order=k, basis="gauss")
+    m3 = synth.Mesh(3, [4, 2, 3], [0, 0, 0], [20e3, 5e3, 10e3], [0, 0, 1], k, "gauss")
+    p1 = k + 1
+    U2 = c2.U.copy()
+    U2[2] += 0.3                                           # some horizontal wind as well
+    U3 = np.zeros((6, m3.ne, m3.npe))
+    A = U2.reshape(5, 3, 4, p1, p1)                        # v, ez, ex, l, i
+    for vv, v3 in zip(range(5), [0, 1, 2, 4, 5]):
+        B = U3[v3].reshape(3, 2, 4, p1, p1, p1)            # ez, ey, ex, l, j, i
+        for ey in range(2):
+            for jj in range(p1):
+                B[:, ey, :, :, jj, :] = A[vv]
+    o2 = O.Oracle.for_case(c2)
+    o3 = O.Oracle(m3, O.default_params(g=c2.g), 6, c2.bg)
+    R2 = o2.rhs(U2).reshape(5, 3, 4, p1, p1)
+    R3 = o3.rhs(U3).reshape(6, 3, 2, 4, p1, p1, p1)
+    for vv, v3 in zip(range(5), [0, 1, 2, 4, 5]):
+        for ey in range(2):
+            for jj in range(p1):
+                np.testing.assert_allclose(R3[v3][:, ey, :, :, jj, :], R2[vv], rtol=1e-11,
+                                           atol=1e-11 * np.abs(R2[vv]).max())
+    assert np.abs(R3[3]).max() < 1e-9 * np.abs(R2[3]).max()
+
+
+def test_sponge_by_projection_keeps_total_density():
+    # the sponge of the modal basis is the L2 projection of the pointwise
+    # update: the integral of rho_d' + rho_m' + rho_r' is unchanged, elements
+    # entirely below z_D are untouched and the momentum above is damped
+    c = synth.warm_rain_3d(n=(3, 3, 4), order=2, basis="gauss")
+    o = O.Oracle.for_case(c, sponge_zD=5.0e3, sponge_alpha=0.5)
+    U1 = o.sponge(c.U)
+    W = node_weights(c.mesh)
+    tot = lambda U: np.sum(W * (U[0] + U[1] + U[2]))
+    assert abs(tot(U1) - tot(c.U)) < 1e-13 * np.sum(W * np.abs(c.U[1]))
+    ez = np.arange(c.mesh.ne) // 9
+    below = ez < 2                                         # elements under 5 km
+    for v in range(7):                                     # to rounding of the projection
+        np.testing.assert_allclose(U1[v, below], c.U[v, below], rtol=0,
+                                   atol=1e-13 * np.abs(c.U[v]).max())
+    above = ez == 3
+    assert np.all(np.abs(U1[3:6, above]).sum() < 0.9 * np.abs(c.U[3:6, above]).sum())
