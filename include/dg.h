@@ -16,7 +16,9 @@
  *   - diagonal mass matrix and the SSPRK(4,3) time step (Section 3.3).
  * The spatial basis is nodal: tensor-product Gauss-Lobatto points on
  * structured boxes, which double as quadrature points (lumped, diagonal
- * mass); the L2 projection of Section 3.4 is then the identity.
+ * mass); the L2 projection of Section 3.4 is then the identity.  The
+ * paper's own Legendre basis with Gauss quadrature is selectable
+ * (dg_params.basis).
  *
  * Memory and ownership
  *   All state arrays passed to the hot calls are DEVICE pointers owned by the
@@ -69,6 +71,7 @@ enum { DG_PERIODIC = 0, DG_SLIPWALL = 1 };       /* boundary type per axis     *
 enum { DG_FP64 = 0, DG_FP32_BULK = 1 };          /* precision of U and flux    */
 enum { DG_SSPRK43 = 0, DG_SSPRK33 = 1 };          /* time integrator           */
 enum { DG_VR_CONST = 0, DG_VR_COSMO = 1 };       /* terminal rain speed model  */
+enum { DG_BASIS_LOBATTO = 0, DG_BASIS_GAUSS = 1 }; /* spatial basis (dg_params) */
 
 /* Structured box mesh; axis dim-1 is vertical (gravity along -e_z).  bc[a]
  * applies to both ends of axis a. */
@@ -100,6 +103,18 @@ typedef struct {
    * off; 0 < alpha <= 1 and zD below every member's top otherwise. */
   double sponge_zD;           /* m, bottom of the sponge layer                 */
   double sponge_alpha;        /* strength in [0, 1]                             */
+  /* Spatial basis of Q^k.  DG_BASIS_LOBATTO (default): nodes at the k+1
+   * Gauss-Lobatto points per axis, which double as quadrature points (lumped
+   * mass).  DG_BASIS_GAUSS: the paper's own discretisation (Section 3.1,
+   * Legendre modes with their exact diagonal mass, Gauss-Legendre quadrature
+   * of k+1 points per axis; Section 3.4, split at the quadrature points and
+   * L2 projection of T and rho_v), held by its values at the Gauss points:
+   * U[v][e][n] and the background arrays are then values at the Gauss
+   * points, and face fluxes use the traces of U', T and rho_v along each
+   * normal line.  With DG_BASIS_GAUSS the adjoint calls dg_rhs_vjp and
+   * dg_rk_step_vjp return DG_EUNSUPPORTED, and dg_reduce_mass leaves its
+   * wall-flux entry NaN. */
+  int basis;                  /* DG_BASIS_LOBATTO or DG_BASIS_GAUSS             */
 } dg_params;
 
 typedef struct {

@@ -70,6 +70,7 @@ struct dg_handle {
   void* stage_x[4] = {nullptr, nullptr, nullptr, nullptr};          // adjoint workspace
   void* stage_w = nullptr;       // adjoint of the step's end state through the sponge
   double* sponge_d = nullptr;    // sponge blending factor per vertical node index
+  double* bgf_d = nullptr;       // Gauss basis: background traces on horizontal faces
   bool sponge = false;
   double* auxT = nullptr;
   double* auxS = nullptr;
@@ -150,6 +151,7 @@ extern "C" void dg_default_params(dg_params* p) {
   p->rho_w = 1000.0; p->N0r = 8.0e6; p->v0r = 130.0; p->q_au = 0.0;
   p->precision = DG_FP64; p->rk = DG_SSPRK43;
   p->newton_rtol = 1e-14; p->newton_maxit = 30;
+  p->basis = DG_BASIS_LOBATTO;
 }
 
 // Lobatto nodes in closed form (k <= 4), weights 2 / (k (k+1) P_k(x)^2) and the
@@ -195,13 +197,69 @@ static void lobatto_tables(int k, double* w, double* Dhat) {
     for (int a = 0; a < p1; ++a) Dhat[i * p1 + a] = w[a] * Dm[a][i] / w[i];
 }
 
+// Gauss-Legendre nodes and weights of the (k+1)-point rule in closed form
+// (k <= 4), the collocation derivative matrix on them from barycentric
+// weights, the weak-form matrix Dhat[i][a] = w_a D_ai / w_i, and the values of
+// the Lagrange basis at the element ends, l_i(-1) and l_i(+1).
+static void gauss_tables(int k, double* x, double* w, double* Dhat, double* lm, double* lp) {
+  const int p1 = k + 1;
+  switch (k) {
+    case 1: x[1] = 1.0 / std::sqrt(3.0); w[0] = w[1] = 1.0; break;
+    case 2: x[2] = std::sqrt(0.6); x[1] = 0.0; w[1] = 8.0 / 9.0; w[0] = w[2] = 5.0 / 9.0; break;
+    case 3: {
+      const double r = 2.0 / 7.0 * std::sqrt(6.0 / 5.0);
+      x[2] = std::sqrt(3.0 / 7.0 - r); x[3] = std::sqrt(3.0 / 7.0 + r);
+      w[1] = w[2] = (18.0 + std::sqrt(30.0)) / 36.0;
+      w[0] = w[3] = (18.0 - std::sqrt(30.0)) / 36.0;
+      break;
+    }
+    default: {
+      const double r = 2.0 * std::sqrt(10.0 / 7.0);
+      x[2] = 0.0; x[3] = std::sqrt(5.0 - r) / 3.0; x[4] = std::sqrt(5.0 + r) / 3.0;
+      w[2] = 128.0 / 225.0;
+      w[1] = w[3] = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0;
+      w[0] = w[4] = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
+      break;
+    }
+  }
+  for (int i = 0; i < p1 / 2; ++i) x[i] = -x[k - i];
+  double lam[kMaxP1];
+  for (int i = 0; i < p1; ++i) {
+    lam[i] = 1.0;
+    for (int m = 0; m < p1; ++m)
+      if (m != i) lam[i] /= (x[i] - x[m]);
+  }
+  double Dm[kMaxP1][kMaxP1];   // Dm[a][i] = l_i'(x_a)
+  for (int a = 0; a < p1; ++a) {
+    double diag = 0.0;
+    for (int i = 0; i < p1; ++i) {
+      if (i == a) continue;
+      Dm[a][i] = lam[i] / lam[a] / (x[a] - x[i]);
+      diag += 1.0 / (x[a] - x[i]);
+    }
+    Dm[a][a] = diag;
+  }
+  for (int i = 0; i < p1; ++i)
+    for (int a = 0; a < p1; ++a) Dhat[i * p1 + a] = w[a] * Dm[a][i] / w[i];
+  for (int i = 0; i < p1; ++i) {
+    double vm = 1.0, vp = 1.0;
+    for (int m = 0; m < p1; ++m)
+      if (m != i) {
+        vm *= (-1.0 - x[m]) / (x[i] - x[m]);
+        vp *= (1.0 - x[m]) / (x[i] - x[m]);
+      }
+    lm[i] = vm;
+    lp[i] = vp;
+  }
+}
+
 static void free_all(dg_handle* h) {
   auto F = [](void* p) { if (p) (void)hipFree(p); };
   F(h->mem_d); F(h->items_d); F(h->ka_d);
   for (auto& b : h->bg_d) F(b);
   for (auto& b : h->stage) F(b);
   for (auto& b : h->stage_x) F(b);
-  F(h->stage_w); F(h->sponge_d);
+  F(h->stage_w); F(h->sponge_d); F(h->bgf_d);
   F(h->auxT); F(h->auxS); F(h->auxT2); F(h->auxS2);
   F(h->auxT3); F(h->auxS3); F(h->auxT4); F(h->auxS4);
   F(h->dt_d); F(h->partial); F(h->red_out); F(h->stats);
@@ -286,6 +344,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   if (p->rk != DG_SSPRK43 && p->rk != DG_SSPRK33) return fail(DG_EINVAL, "bad rk scheme");
   if (p->vr_mode != DG_VR_CONST && p->vr_mode != DG_VR_COSMO) return fail(DG_EINVAL, "bad vr_mode");
   if (!(p->newton_rtol > 0) || p->newton_maxit < 1) return fail(DG_EINVAL, "bad Newton settings");
+  if (p->basis != DG_BASIS_LOBATTO && p->basis != DG_BASIS_GAUSS) return fail(DG_EINVAL, "bad basis");
   if (!(p->sponge_alpha >= 0.0 && p->sponge_alpha <= 1.0) || !std::isfinite(p->sponge_zD))
     return fail(DG_EINVAL, "sponge_alpha must lie in [0, 1] and sponge_zD be finite");
   if (p->sponge_alpha > 0.0)
@@ -306,7 +365,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   int hoff = 0;
   long long items_max = 0;
   double wq[kMaxP1], Dq[kMaxP1 * kMaxP1];
-  lobatto_tables(order, wq, Dq);
+  lobatto_tables(order, wq, Dq);   // md.lift: Lobatto kernels only
   for (int m = 0; m < nmembers; ++m) {
     const dg_mesh& g = meshes[m];
     MemberDesc md{};
@@ -378,6 +437,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
     ok = ok && A(&h->stage_w, h->state_bytes);
     ok = ok && A((void**)&h->sponge_d, sizeof(double) * hoff);
   }
+  if (p->basis == DG_BASIS_GAUSS) ok = ok && A((void**)&h->bgf_d, sizeof(double) * 5 * 2 * (hoff / p1));
   ok = ok && A((void**)&h->dt_d, sizeof(double) * nmembers);
   ok = ok && A((void**)&h->partial, sizeof(double) * 3 * h->items_cap);
   ok = ok && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) == hipSuccess;
@@ -416,7 +476,22 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   a.q_au = p->q_au;
   a.rain = p->rain; a.vr_mode = p->vr_mode;
   a.rtol = p->newton_rtol; a.maxit = p->newton_maxit;
-  lobatto_tables(order, a.w, a.Dhat);
+  a.basis = p->basis;
+  double xnode[kMaxP1];
+  if (p->basis == DG_BASIS_GAUSS) {
+    gauss_tables(order, xnode, a.w, a.Dhat, a.gl_m, a.gl_p);
+    for (int i = 0; i <= order; ++i) {
+      a.lift_m[i] = a.gl_m[i] / a.w[i];
+      a.lift_p[i] = a.gl_p[i] / a.w[i];
+    }
+    a.bgf = h->bgf_d;
+    a.bgf_n = 2 * (hoff / p1);
+  } else {
+    lobatto_tables(order, a.w, a.Dhat);
+    lobatto_nodes(order, xnode);
+    a.bgf = nullptr;
+    a.bgf_n = 0;
+  }
   a.mem = h->mem_d;
   a.items = h->items_d;
   a.nitems = (int)h->items.size();
@@ -429,9 +504,8 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   a.sponge = nullptr;
   if (h->sponge) {
     // blending factor at every node height of every member (the L2 projection
-    // onto the Lobatto nodal basis is the nodal value)
-    double xl[kMaxP1];
-    lobatto_nodes(order, xl);
+    // onto the nodal basis, Lobatto or Gauss, takes the nodal value)
+    const double* xl = xnode;
     std::vector<double> dl(hoff, 0.0);
     for (int m = 0; m < nmembers; ++m) {
       const dg_mesh& g = meshes[m];
@@ -494,6 +568,36 @@ __global__ void bg_pressure_kernel(KArgs a, int i0, int n, int rain) {
   const_cast<double*>(a.bg_p)[i] = (rd * a.Rd + rv * a.Rv) * s.T;
 }
 
+// Background traces on the horizontal faces of the Gauss basis, for the
+// element rows [r0, r0 + nrows) of the concatenated columns: rho_d, rho_m,
+// rho_r and E interpolated from the row's k+1 node heights to its bottom and
+// top, and p the equation of state of the traced split background (T and
+// rho_v traced as well), so that the unperturbed state has p' = 0 on faces.
+__global__ void bg_face_kernel(KArgs a, int K, int r0, int nrows, int rain) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= 2 * nrows) return;
+  const int r = r0 + i / 2, side = i % 2;
+  const int P1 = K + 1;
+  const double* L = side ? a.gl_p : a.gl_m;
+  double t[6] = {0, 0, 0, 0, 0, 0};
+  for (int l = 0; l < P1; ++l) {
+    const int iz = r * P1 + l;
+    const double rd = a.bg_rd[iz], rm = a.bg_rm[iz], rr = rain ? a.bg_rr[iz] : 0.0, E = a.bg_E[iz];
+    const SplitOut s = split_point(a, rd, rm, rr, E, 0.0);
+    const double w = L[l];
+    t[0] += w * rd;
+    t[1] += w * rm;
+    t[2] += w * rr;
+    t[3] += w * E;
+    t[4] += w * s.T;
+    t[5] += w * fmin(s.rvs, rm);
+  }
+  double* bgf = const_cast<double*>(a.bgf);
+  const int at = 2 * r + side;
+  for (int f = 0; f < 4; ++f) bgf[f * a.bgf_n + at] = t[f];
+  bgf[4 * a.bgf_n + at] = (t[0] * a.Rd + t[5] * a.Rv) * t[4];
+}
+
 extern "C" dg_status dg_set_background(dg_handle* h, int member, const double* rd, const double* rm,
                                        const double* rr, const double* E) {
   if (!h) return fail(DG_EINVAL, "null handle");
@@ -517,6 +621,14 @@ extern "C" dg_status dg_set_background(dg_handle* h, int member, const double* r
   for (int i = 0; i < n; ++i)
     if (!std::isfinite(pb[i]) || !(pb[i] > 0))
       return fail(DG_EINVAL, "background state at index %d has no valid temperature", i);
+  if (h->P.basis == DG_BASIS_GAUSS) {
+    const int p1 = h->order + 1;
+    const int nrows = n / p1;
+    hipLaunchKernelGGL(bg_face_kernel, dim3((2 * nrows + 127) / 128), dim3(128), 0, 0, h->ka, h->order,
+                       off / p1, nrows, h->rain);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipDeviceSynchronize());
+  }
   h->bg_set[member] = 1;
   return DG_OK;
 }
@@ -673,6 +785,7 @@ extern "C" dg_status dg_reduce_mass(dg_handle* h, int member, const void* U, dou
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(out3, h->red_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
+  if (h->P.basis != DG_BASIS_LOBATTO) out3[2] = std::nan("");   // no node layer on the wall
   return DG_OK;
 }
 
@@ -713,6 +826,7 @@ static bool do_vjp(dg_handle* h, const void* U, const double* aT, const double* 
 extern "C" dg_status dg_rhs_vjp(dg_handle* h, const void* U, const void* lam, void* Ub, hipStream_t s) {
   dg_status st = ready(h);
   if (st != DG_OK) return st;
+  if (h->P.basis != DG_BASIS_LOBATTO) return fail(DG_EUNSUPPORTED, "adjoints exist for the Lobatto basis only");
   if (!U || !lam || !Ub) return fail(DG_EINVAL, "null pointer");
   if (Ub == U || Ub == lam) return fail(DG_EINVAL, "U_bar must not alias U or dUdt_bar");
   if (!do_split(h, U, nullptr, h->auxT, h->auxS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
@@ -752,6 +866,7 @@ extern "C" dg_status dg_rk_step_vjp(dg_handle* h, const void* Un, const void* W,
                                     hipStream_t s) {
   dg_status st = ready(h);
   if (st != DG_OK) return st;
+  if (h->P.basis != DG_BASIS_LOBATTO) return fail(DG_EUNSUPPORTED, "adjoints exist for the Lobatto basis only");
   if (!Un || !W || !Ub0 || !dt) return fail(DG_EINVAL, "null pointer");
   if (Ub0 == Un || Ub0 == W) return fail(DG_EINVAL, "U_n_bar must not alias U_n or U_np1_bar");
   st = upload_dt(h, dt, s);

@@ -42,9 +42,20 @@ struct KArgs {
   int rain, vr_mode;
   double rtol;
   int maxit;
-  // Lobatto tables: Dhat[i*(k+1)+a] = w_a D_ai / w_i, weights w
+  // nodal tables of the basis (Lobatto, or Gauss for basis 1):
+  // Dhat[i*(k+1)+a] = w_a D_ai / w_i, weights w
   double Dhat[kMaxP1 * kMaxP1];
   double w[kMaxP1];
+  // basis 1 (Gauss nodes): traces l_i(-1), l_i(+1) of the Lagrange basis and
+  // the lifting weights l_i(-+1) / w_i
+  int basis;
+  double gl_m[kMaxP1], gl_p[kMaxP1];
+  double lift_m[kMaxP1], lift_p[kMaxP1];
+  // basis 1: background traces on the horizontal faces, bgf[f * bgf_n + 2 r + s]
+  // for field f = (rho_d, rho_m, rho_r, E, p), element row r of the
+  // concatenated columns (hoff / (k+1) + ez) and side s (0 bottom, 1 top)
+  const double* bgf;
+  int bgf_n;
   // members and work items (member, first element) of EPB elements each
   const MemberDesc* mem;
   const Item* items;

@@ -315,25 +315,26 @@ struct Pt {
   R rc, dvs, Tm;    // rho_c, rho_vs(T) - rho_v, T - T_ref (rain only)
 };
 
-// Full state from the stored perturbation U at vertical index iz and the
-// split result (T, rho_vs(T)).  The reconstruction is FP64.
+// Full state from the perturbation Uq, the temperature T, the vapour density
+// rho_v and the background (rho_d, rho_m, rho_r, E, p) at the point; rho_vs
+// enters only the evaporation source.  The reconstruction is FP64.
 template <typename R, int D, int RAIN>
-__device__ __forceinline__ void eval_point(const KArgs& a, const R* Uq, double T, double rvs, int iz,
-                                           Pt<R, D, RAIN>& q) {
+__device__ __forceinline__ void eval_core(const KArgs& a, const R* Uq, double T, double rv, double rvs,
+                                          double bd, double bm, double br, double bE, double bp,
+                                          Pt<R, D, RAIN>& q) {
   using V = Vars<D, RAIN>;
-  const double rd = a.bg_rd[iz] + (double)Uq[V::RD];
-  const double rm = a.bg_rm[iz] + (double)Uq[V::RM];
-  const double rr = RAIN ? a.bg_rr[iz] + (double)Uq[V::RR] : 0.0;
-  const double rv = fmin(rvs, rm);
+  const double rd = bd + (double)Uq[V::RD];
+  const double rm = bm + (double)Uq[V::RM];
+  const double rr = RAIN ? br + (double)Uq[V::RR] : 0.0;
   const double rc = rm - rv;
   const double gasR = rd * a.Rd + rv * a.Rv;
   const double p = gasR * T;
-  const double ppd = p - a.bg_p[iz];
+  const double ppd = p - bp;
   const double rho = rd + rm + rr;
   const double Cv = a.cvd * rd + a.cvv * rv + a.cl * (rc + rr);
   q.rd = (R)rd; q.rm = (R)rm; q.rr = (R)rr; q.rho = (R)rho;
   q.pp = (R)ppd;
-  q.H = (R)(a.bg_E[iz] + a.bg_p[iz] + (double)Uq[V::E] + ppd);
+  q.H = (R)(bE + bp + (double)Uq[V::E] + ppd);
   R uu = R(0);
   const R irho = inv_b(q.rho);
   for (int i = 0; i < D; ++i) {
@@ -355,6 +356,18 @@ __device__ __forceinline__ void eval_point(const KArgs& a, const R* Uq, double T
     q.vr = R(0); q.rrvr = R(0); q.rain_e = R(0);
     q.rc = R(0); q.dvs = R(0); q.Tm = R(0);
   }
+}
+
+// Full state at a node from the stored perturbation U at vertical index iz and
+// the split result (T, rho_vs(T)): rho_v = min(rho_vs, rho_m).
+template <typename R, int D, int RAIN>
+__device__ __forceinline__ void eval_point(const KArgs& a, const R* Uq, double T, double rvs, int iz,
+                                           Pt<R, D, RAIN>& q) {
+  using V = Vars<D, RAIN>;
+  const double rm = a.bg_rm[iz] + (double)Uq[V::RM];
+  const double rv = fmin(rvs, rm);
+  eval_core<R, D, RAIN>(a, Uq, T, rv, rvs, a.bg_rd[iz], a.bg_rm[iz], RAIN ? a.bg_rr[iz] : 0.0, a.bg_E[iz],
+                        a.bg_p[iz], q);
 }
 
 // Physical flux in direction j (Section 2.3 perturbation form).

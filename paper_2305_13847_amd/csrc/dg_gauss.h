@@ -1,0 +1,278 @@
+// Right-hand side / stage kernel of the Gauss basis: nodes at the k+1
+// Gauss-Legendre points per axis.  That nodal basis spans the same Q^k as the
+// paper's Legendre modes, its quadrature at the nodes is the paper's Gauss
+// rule, the mass matrix is diagonal and exact, and the L2 projection of the
+// split results onto Q^k (Section 3.4) is their nodal value.  What changes
+// against the Lobatto kernels is the face: no node lies on it, so every face
+// quadrature point takes the traces of U', T and rho_v along its normal line
+// (k+1 nodes per side), and the face flux is lifted back to every node of
+// that line.
+//
+// A block owns a work item of EPB elements, one thread per node:
+//   1. node pass: the point state, its fluxes (LDS) and the perturbation, T
+//      and rho_v (LDS), then the volume term and the sources;
+//   2. face pass: the block's EPB * 2D * (k+1)^(D-1) face points, each with
+//      its own trace from LDS and the neighbour's from global memory, the
+//      Lax-Friedrichs flux with normal +e_J into LDS;
+//   3. lifting, the stage update and the split of the new state.
+#pragma once
+#include "dg_kernels.h"
+
+namespace dgm {
+
+template <int K, int D>
+struct GaussShape {
+  static constexpr int P1 = K + 1;
+  static constexpr int NF = (D == 2) ? P1 : P1 * P1;   // quadrature points of one face
+  static constexpr int NFE = 2 * D * NF;                // face points of one element
+};
+
+// Node of an element on the J-line through face point fp at position a along J.
+// The face point enumerates the other axes, the lower axis fastest.
+template <int K, int D, int J>
+__device__ __forceinline__ int line_node(int fp, int a) {
+  constexpr int P1 = K + 1;
+  if constexpr (D == 2) {
+    return J == 0 ? a + P1 * fp : fp + P1 * a;
+  } else {
+    const int u = fp % P1, w = fp / P1;
+    if constexpr (J == 0) return a + P1 * (u + P1 * w);
+    else if constexpr (J == 1) return u + P1 * (a + P1 * w);
+    else return u + P1 * (w + P1 * a);
+  }
+}
+
+// vertical node index (within the element) of face point fp of a face normal
+// to a horizontal axis J < D-1
+template <int K, int D, int J>
+__device__ __forceinline__ int face_level(int fp) {
+  return D == 2 ? fp : fp / (K + 1);
+}
+
+// LF flux with normal +e_J at face point fp on side `side` (0: xi_J = -1,
+// 1: xi_J = +1) of element le of the item.
+template <typename R, int K, int D, int RAIN, int J>
+__device__ __forceinline__ void gauss_face(const KArgs& a, const MemberDesc& md, const Item& item, int le,
+                                           int side, int fp, const R* sU, const double* sT,
+                                           const double* sRv, const double (*sL)[kMaxP1],
+                                           const R* __restrict__ U, const double* __restrict__ auxT,
+                                           const double* __restrict__ auxS, R* Fs) {
+  using S = Shape<K, D, block_threads<R>()>;
+  using V = Vars<D, RAIN>;
+  constexpr int P1 = S::P1, NP = S::NP, NV = V::NV, NT = S::NT;
+  const unsigned N = a.nnodes;
+  // own trace from the block's tiles
+  R Uo[NV];
+  double To = 0.0, Rvo = 0.0;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Uo[v] = R(0);
+#pragma unroll
+  for (int i = 0; i < P1; ++i) {
+    const int nd = le * NP + line_node<K, D, J>(fp, i);
+    const double w = sL[side][i];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Uo[v] += (R)w * sU[v * NT + nd];
+    To += w * sT[nd];
+    Rvo += w * sRv[nd];
+  }
+  const ElemCoord<D> ec = item_coord<D>(md, item, le);
+  const int e = item.e0 + le;
+  const int c = ec.c[J];
+  const bool at_end = side ? (c == md.n[J] - 1) : (c == 0);
+  const bool wall = at_end && md.bc[J] == 1;
+  int cn = side ? c + 1 : c - 1;
+  if (cn < 0) cn += md.n[J];
+  if (cn >= md.n[J]) cn -= md.n[J];
+  // background at the face point, own and neighbour side
+  double bo[5], bn[5];
+  int izf = 0;
+  if constexpr (J == D - 1) {
+    const int r0 = md.hoff / P1;
+#pragma unroll
+    for (int f = 0; f < 5; ++f) {
+      bo[f] = a.bgf[f * a.bgf_n + 2 * (r0 + c) + side];
+      bn[f] = a.bgf[f * a.bgf_n + 2 * (r0 + cn) + 1 - side];
+    }
+  } else {
+    izf = md.hoff + ec.c[D - 1] * P1 + face_level<K, D, J>(fp);
+    bo[0] = a.bg_rd[izf]; bo[1] = a.bg_rm[izf]; bo[2] = RAIN ? a.bg_rr[izf] : 0.0;
+    bo[3] = a.bg_E[izf]; bo[4] = a.bg_p[izf];
+#pragma unroll
+    for (int f = 0; f < 5; ++f) bn[f] = bo[f];
+  }
+  // neighbour trace: the ghost of the own trace on a slip wall, otherwise
+  // interpolated along the neighbour's line at its opposite side
+  R Un[NV];
+  double Tn = 0.0, Rvn = 0.0;
+  if (wall) {
+    // the ghost keeps the own background (cn wrapped to the far end of the column)
+#pragma unroll
+    for (int f = 0; f < 5; ++f) bn[f] = bo[f];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = Uo[v];
+    Un[V::M0 + J] = -Uo[V::M0 + J];
+    Tn = To;
+    Rvn = Rvo;
+  } else {
+    const int en = e + (cn - c) * elem_stride(md, J);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Un[v] = R(0);
+#pragma unroll
+    for (int i = 0; i < P1; ++i) {
+      const unsigned gn = (unsigned)(md.eoff + en) * NP + line_node<K, D, J>(fp, i);
+      const double w = sL[1 - side][i];
+      R u[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = ld(U, N, v, gn);
+      const int izn = (J == D - 1) ? md.hoff + cn * P1 + i : izf;
+      const double rvi = fmin(ld(auxS, N, 0, gn), a.bg_rm[izn] + (double)u[V::RM]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Un[v] += (R)w * u[v];
+      Tn += w * ld(auxT, N, 0, gn);
+      Rvn += w * rvi;
+    }
+  }
+  Pt<R, D, RAIN> qo, qn;
+  eval_core<R, D, RAIN>(a, Uo, To, Rvo, Rvo, bo[0], bo[1], bo[2], bo[3], bo[4], qo);
+  eval_core<R, D, RAIN>(a, Un, Tn, Rvn, Rvn, bn[0], bn[1], bn[2], bn[3], bn[4], qn);
+  // minus side = lower coordinate along J
+  const Pt<R, D, RAIN>& qm = side ? qo : qn;
+  const Pt<R, D, RAIN>& qp = side ? qn : qo;
+  const R* Um = side ? Uo : Un;
+  const R* Up = side ? Un : Uo;
+  R Fm[NV], Fp[NV];
+  flux<R, D, RAIN, J>(qm, Fm);
+  flux<R, D, RAIN, J>(qp, Fp);
+  const R lm = wave_speed<R, D, RAIN, J>(qm), lp = wave_speed<R, D, RAIN, J>(qp);
+  const R Lam = lm >= lp ? lm : lp;
+  const R half = R(0.5);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Fs[v] = half * (Fm[v] + Fp[v]) + half * Lam * (Um[v] - Up[v]);
+}
+
+template <typename R, int K, int D, int RAIN, int MODE>
+__global__ void __launch_bounds__(256)
+rhs_gauss_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
+                 const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
+                 const double* __restrict__ dt_m, double c0, double c1, double c2,
+                 double* __restrict__ oT, double* __restrict__ oS, int flags) {
+  using S = Shape<K, D, block_threads<R>()>;
+  using V = Vars<D, RAIN>;
+  using G = GaussShape<K, D>;
+  constexpr int P1 = S::P1, NP = S::NP, NV = V::NV, NT = S::NT;
+  constexpr int NF = G::NF, NFE = G::NFE, NFB = S::EPB * NFE;
+  __shared__ R sF[D * NV * NT];
+  __shared__ R sU[NV * NT];
+  __shared__ double sT[NT], sRv[NT];
+  __shared__ R sFs[NV * NFB];
+  __shared__ R sD[P1 * P1];
+  __shared__ double sL[2][kMaxP1];
+  const int t = threadIdx.x;
+  if (t < P1 * P1) sD[t] = (R)a.Dhat[t];
+  if (t < P1) {
+    sL[0][t] = a.gl_m[t];
+    sL[1][t] = a.gl_p[t];
+  }
+  const int epb = (int)blockDim.x / NP;
+  const ItemWalk walk(a.nitems);
+#pragma clang loop unroll(disable)
+  for (int kk = 0;; ++kk) {
+    const int it_ = walk.item(kk);
+    if (it_ < 0) break;
+    const Item item = a.items[it_];
+    const MemberDesc& md = a.mem[item.member];
+    const int le = t / NP, n = t - le * NP;
+    const int e = item.e0 + le;
+    const bool active = e < md.ne;
+    const unsigned N = a.nnodes;
+    const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
+    const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
+    int idx[3];
+    idx[0] = n % P1;
+    idx[1] = (n / P1) % P1;
+    idx[2] = (D == 3) ? n / (P1 * P1) : 0;
+    const int iz = md.hoff + ec.c[D - 1] * P1 + idx[D - 1];
+    // 1. node pass
+    R Uq[NV];
+    double T = 300.0, rvs = 0.0;
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Uq[v] = ld(U, N, v, g);
+      T = ld(auxT, N, 0, g);
+      rvs = ld(auxS, N, 0, g);
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Uq[v] = R(0);
+    }
+    Pt<R, D, RAIN> q;
+    eval_point<R, D, RAIN>(a, Uq, T, rvs, active ? iz : md.hoff, q);
+    stage_flux<R, K, D, RAIN, 0>(q, sF);
+    stage_flux<R, K, D, RAIN, 1>(q, sF + NV * NT);
+    if constexpr (D == 3) stage_flux<R, K, D, RAIN, 2>(q, sF + 2 * NV * NT);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sU[v * NT + t] = Uq[v];
+    sT[t] = T;
+    sRv[t] = active ? fmin(rvs, a.bg_rm[iz] + (double)Uq[V::RM]) : 0.0;
+    __syncthreads();
+    R Rv[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Rv[v] = R(0);
+    if (active) {
+      volume_dir<R, K, D, RAIN, 0>(md, idx[0], sF, Rv, sD, t);
+      volume_dir<R, K, D, RAIN, 1>(md, idx[1], sF + NV * NT, Rv, sD, t);
+      if constexpr (D == 3) volume_dir<R, K, D, RAIN, 2>(md, idx[2], sF + 2 * NV * NT, Rv, sD, t);
+      sources<R, D, RAIN>(a, Uq, q, Rv);
+    }
+    // 2. face pass
+    for (int task = t; task < epb * NFE; task += (int)blockDim.x) {
+      const int fle = task / NFE;
+      const int r = task - fle * NFE;
+      const int f = r / NF;
+      const int fp = r - f * NF;
+      const int J = f >> 1, side = f & 1;
+      R Fs[NV];
+      if (item.e0 + fle < md.ne) {
+        if (J == 0) gauss_face<R, K, D, RAIN, 0>(a, md, item, fle, side, fp, sU, sT, sRv, sL, U, auxT, auxS, Fs);
+        else if (J == 1 || D == 2)
+          gauss_face<R, K, D, RAIN, 1>(a, md, item, fle, side, fp, sU, sT, sRv, sL, U, auxT, auxS, Fs);
+        else if constexpr (D == 3)
+          gauss_face<R, K, D, RAIN, 2>(a, md, item, fle, side, fp, sU, sT, sRv, sL, U, auxT, auxS, Fs);
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Fs[v] = R(0);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sFs[v * NFB + task] = Fs[v];
+    }
+    __syncthreads();
+    // 3. lifting: + l_i(-1)/w_i F*(minus face) - l_i(+1)/w_i F*(plus face)
+    int iters = 0, bad = 0;
+    if (active) {
+#pragma unroll
+      for (int J = 0; J < D; ++J) {
+        const int i = idx[J];
+        int fpJ;
+        if (D == 2) fpJ = (J == 0) ? idx[1] : idx[0];
+        else fpJ = (J == 0) ? idx[1] + P1 * idx[2] : (J == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
+        const int base = le * NFE + 2 * J * NF + fpJ;
+        const R km = (R)(md.two_over_h[J] * a.lift_m[i]);
+        const R kp = (R)(md.two_over_h[J] * a.lift_p[i]);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Rv[v] += km * sFs[v * NFB + base] - kp * sFs[v * NFB + base + NF];
+      }
+      R U0q[NV];
+      const double dtm = (MODE != 0) ? dt_m[item.member] : 0.0;
+      if (MODE != 0 && c0 != 0.0) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) U0q[v] = ld(U0, N, v, g);
+      }
+      double bg[4] = {a.bg_rd[iz], a.bg_rm[iz], RAIN ? a.bg_rr[iz] : 0.0, a.bg_E[iz]};
+      stage_epilogue<R, D, RAIN, MODE>(a, bg, iz, g, N, Uq, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS,
+                                       flags, iters, bad);
+    }
+    if (MODE == 2) record_stats(a, iters, bad);
+    __syncthreads();   // the tiles are reused by the next item
+  }
+}
+
+}  // namespace dgm

@@ -815,7 +815,8 @@ mass_kernel(KArgs a, int item0, const R* __restrict__ U, double* __restrict__ pa
     for (int j = 0; j < D; ++j) w *= a.w[idx[j]];
     md_ = w * (double)U[V::RD * N + g];
     mw = w * ((double)U[V::RM * N + g] + (RAIN ? (double)U[V::RR * N + g] : 0.0));
-    if (RAIN && md.bc[D - 1] == 1) {
+    // (Lobatto nodes only: the wall is a node layer there)
+    if (RAIN && md.bc[D - 1] == 1 && a.basis == 0) {
       const ElemCoord<D> ec = item_coord<D>(md, item, le);
       const int l = idx[D - 1];
       const bool bottom = ec.c[D - 1] == 0 && l == 0;

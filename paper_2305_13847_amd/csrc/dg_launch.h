@@ -3,6 +3,7 @@
 #pragma once
 #include <type_traits>
 #include "dg_kernels.h"
+#include "dg_gauss.h"
 #include "dg_vjp.h"
 
 namespace dgm {
@@ -74,7 +75,12 @@ struct Launch {
                      (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, flags)
       // the persistent (looping) variant only when the grid is smaller than the items
       const bool persist = (int)grid.x < grid_for_items(a.nitems);
-      if (mode == 0) DGM_RHS(rhs_kernel, 0);
+      if (a.basis == 1) {
+        // Gauss nodes: one kernel walks the items for any grid
+        if (mode == 0) DGM_RHS(rhs_gauss_kernel, 0);
+        else if (mode == 1) DGM_RHS(rhs_gauss_kernel, 1);
+        else DGM_RHS(rhs_gauss_kernel, 2);
+      } else if (mode == 0) DGM_RHS(rhs_kernel, 0);
       else if (mode == 1) DGM_RHS(rhs_kernel, 1);
       else if (!persist) DGM_RHS(rhs_kernel, 2);
       else

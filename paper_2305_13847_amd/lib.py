@@ -22,6 +22,8 @@ DG_PERIODIC, DG_SLIPWALL = 0, 1
 DG_FP64, DG_FP32_BULK = 0, 1
 DG_SSPRK43, DG_SSPRK33 = 0, 1
 DG_VR_CONST, DG_VR_COSMO = 0, 1
+DG_BASIS_LOBATTO, DG_BASIS_GAUSS = 0, 1
+BASES = {"lobatto": DG_BASIS_LOBATTO, "gauss": DG_BASIS_GAUSS}
 
 
 class DGError(RuntimeError):
@@ -42,7 +44,7 @@ class dg_params(ct.Structure):
                 ("rho_w", ct.c_double), ("N0r", ct.c_double), ("v0r", ct.c_double),
                 ("q_au", ct.c_double), ("precision", ct.c_int), ("rk", ct.c_int),
                 ("newton_rtol", ct.c_double), ("newton_maxit", ct.c_int),
-                ("sponge_zD", ct.c_double), ("sponge_alpha", ct.c_double)]
+                ("sponge_zD", ct.c_double), ("sponge_alpha", ct.c_double), ("basis", ct.c_int)]
 
 
 class dg_stats(ct.Structure):
@@ -325,6 +327,7 @@ class DG:
 
 
 def params_for_case(case, precision=DG_FP64, **over) -> dg_params:
+    over.setdefault("basis", BASES[getattr(case.mesh, "basis", "lobatto")])
     return default_params(g=case.g, rain=case.rain, vr_const=case.vr_const, precision=precision, **over)
 
 
