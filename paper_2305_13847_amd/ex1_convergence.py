@@ -3,12 +3,15 @@
 
 Meshes are nested: level r has 30 r x r elements (h = 10 km / r).
 - Every run is stopped at nsnap equidistant times.
-- A coarse solution is interpolated (its own Lagrange basis on its Lobatto
-  nodes) to the nodes of the reference level.
+- A coarse solution is interpolated (its own Lagrange basis on its nodes) to
+  the nodes of the reference level.
 - The error is the l2(L2) norm over the snapshots:
-  sum_i ||x_h(t_i) - x_ref(t_i)||^2_L2, with the reference level's Lobatto
+  sum_i ||x_h(t_i) - x_ref(t_i)||^2_L2, with the reference level's
   quadrature. It is reported per conserved variable, relative to the same
   norm of the reference.
+- The basis is the Lobatto collocation or the paper's Legendre space with
+  Gauss quadrature (held by its values at the Gauss points); the reference
+  run uses the same basis as the levels.
 
 Everything here drives the library through its C ABI (dg_rk_step); torch only
 holds the arrays and does the interpolation.
@@ -39,10 +42,11 @@ def _lagrange(xn: np.ndarray, x: np.ndarray) -> np.ndarray:
     return L
 
 
-def run(r: int, k: int, t_end: float, nsnap: int, prec=lib.DG_FP64, cfl=0.5, log=None, qw=0.02):
+def run(r: int, k: int, t_end: float, nsnap: int, prec=lib.DG_FP64, cfl=0.5, log=None, qw=0.02,
+        basis="lobatto"):
     """Snapshots (nsnap, nvars, ne, npe) on the device of the level-r, order-k run."""
     import torch
-    c = synth.gravity_waves(n=(30 * r, r), order=k, t_end=t_end, cfl=cfl, qw=qw)
+    c = synth.gravity_waves(n=(30 * r, r), order=k, t_end=t_end, cfl=cfl, qw=qw, basis=basis)
     dt_cfl = synth.cfl_dt(c.mesh, 20.0, 0.0, cfl)
     per = int(np.ceil((t_end / nsnap) / dt_cfl))
     dt = t_end / nsnap / per
@@ -64,12 +68,16 @@ def run(r: int, k: int, t_end: float, nsnap: int, prec=lib.DG_FP64, cfl=0.5, log
     return c, torch.stack(snaps), per * nsnap
 
 
-def to_reference(Uc, rc: int, kc: int, rf: int, kf: int):
+def _points(k: int, basis: str) -> np.ndarray:
+    return synth.gauss_points(k) if basis == "gauss" else synth.lobatto_points(k)
+
+
+def to_reference(Uc, rc: int, kc: int, rf: int, kf: int, basis: str = "lobatto"):
     """Interpolate (..., nvars, ne, npe) fields of level rc / order kc onto level rf / order kf."""
     import torch
     s = rf // rc
     assert s * rc == rf
-    xc, xf = synth.lobatto_points(kc), synth.lobatto_points(kf)
+    xc, xf = _points(kc, basis), _points(kf, basis)
     nxc, nzc, nxf, nzf = 30 * rc, rc, 30 * rf, rf
     lead = Uc.shape[:-2]
     A = Uc.reshape(*lead, nzc, nxc, kc + 1, kc + 1)           # [.., ez, ex, j(z), i(x)]
@@ -84,10 +92,11 @@ def to_reference(Uc, rc: int, kc: int, rf: int, kf: int):
     return out.reshape(*lead, nzf * nxf, (kf + 1) ** 2)
 
 
-def l2_sq(F, rf: int, kf: int):
-    """Lobatto-quadrature L2 norm squared of (..., ne, npe) fields on level rf (h = 10 km / rf)."""
+def l2_sq(F, rf: int, kf: int, basis: str = "lobatto"):
+    """L2 norm squared of (..., ne, npe) fields on level rf (h = 10 km / rf), by the
+    quadrature of the basis' nodes."""
     import torch
-    w = synth_weights(kf)
+    w = np.polynomial.legendre.leggauss(kf + 1)[1] if basis == "gauss" else synth_weights(kf)
     h = 10.0e3 / rf
     W = torch.tensor(np.outer(w, w).reshape(-1) * (0.5 * h) ** 2, dtype=F.dtype, device=F.device)
     return (F * F * W).sum(dim=(-2, -1))
@@ -100,17 +109,18 @@ def synth_weights(k: int) -> np.ndarray:
     return 2.0 / (k * (k + 1) * P * P)
 
 
-def study(levels, orders, ref: int, kref: int, t_end: float, nsnap: int, log=print, cfl=0.5, qw=0.02):
+def study(levels, orders, ref: int, kref: int, t_end: float, nsnap: int, log=print, cfl=0.5, qw=0.02,
+          basis="lobatto"):
     import torch
-    log("reference: r=%d (h=%g m), k=%d, cfl %g" % (ref, 10e3 / ref, kref, cfl))
-    cref, Sref, nref = run(ref, kref, t_end, nsnap, log=log, cfl=cfl, qw=qw)
-    norm = torch.sqrt(l2_sq(Sref, ref, kref).sum(dim=0))     # per variable
+    log("reference: r=%d (h=%g m), k=%d, cfl %g, %s basis" % (ref, 10e3 / ref, kref, cfl, basis))
+    cref, Sref, nref = run(ref, kref, t_end, nsnap, log=log, cfl=cfl, qw=qw, basis=basis)
+    norm = torch.sqrt(l2_sq(Sref, ref, kref, basis).sum(dim=0))     # per variable
     rows = []
     for k in orders:
         prev = None
         for r in levels:
-            c, S, n = run(r, k, t_end, nsnap, log=log, cfl=cfl, qw=qw)
-            E = torch.sqrt(l2_sq(to_reference(S, r, k, ref, kref) - Sref, ref, kref).sum(dim=0)) / norm
+            c, S, n = run(r, k, t_end, nsnap, log=log, cfl=cfl, qw=qw, basis=basis)
+            E = torch.sqrt(l2_sq(to_reference(S, r, k, ref, kref, basis) - Sref, ref, kref, basis).sum(dim=0)) / norm
             err = E.cpu().numpy()
             rate = None if prev is None else (np.log(prev / err) / np.log(2.0)).tolist()
             rows.append(dict(k=k, r=r, h=10e3 / r, steps=n, err=err.tolist(), rate=rate))
@@ -130,6 +140,7 @@ def main(argv=None):
     ap.add_argument("--nsnap", type=int, default=30)
     ap.add_argument("--cfl", type=float, default=0.5)
     ap.add_argument("--qw", type=float, default=0.02, help="total water ratio (0: the dry case)")
+    ap.add_argument("--basis", default="lobatto", choices=["lobatto", "gauss"])
     ap.add_argument("--json", default=None, help="write the table here")
     a = ap.parse_args(argv)
     import torch
@@ -139,7 +150,7 @@ def main(argv=None):
     torch.zeros(1, device="cuda")          # the device runtime is up before any handle
     lib.load()
     rows = study(a.levels, a.orders, a.ref, a.kref, a.t_end, a.nsnap,
-                 log=lambda m: print(m, flush=True), cfl=a.cfl, qw=a.qw)
+                 log=lambda m: print(m, flush=True), cfl=a.cfl, qw=a.qw, basis=a.basis)
     if a.json:
         with open(a.json, "w") as f:
             json.dump(dict(args=vars(a), vars=VARS, rows=rows), f, indent=1)

@@ -111,3 +111,22 @@ def test_set_up_saturation_law_is_the_papers():
         dlog = (np.log(es(T + h)) - np.log(es(T - h))) / (2 * h)
         assert dlog == pytest.approx((2.835e6 + (1850.0 - 4218.0) * (T - 273.15)) / (Rv * T * T), rel=1e-7)
         assert synth.paper_rho_vs(T) == pytest.approx(O.rho_vs(P, T), rel=1e-13)
+
+
+@pytest.mark.parametrize("rc,kc", [(2, 2), (4, 3)])
+def test_nested_interpolation_exact_gauss_nodes(rc, kc):
+    from paper_2305_13847_amd import ex1_convergence as ex
+    mc = synth.Mesh(2, [30 * rc, rc], [0, 0], [300e3, 10e3], [0, 1], kc, "gauss")
+    mf = synth.Mesh(2, [30 * 8, 8], [0, 0], [300e3, 10e3], [0, 1], 4, "gauss")
+    rng = np.random.default_rng(rc * 7 + kc)
+    cx, cz = rng.standard_normal(kc + 1), rng.standard_normal(kc + 1)
+
+    def f(mesh):
+        X = synth.node_coords(mesh)
+        return np.polynomial.polynomial.polyval(X[0] / 3e5, cx) * np.polynomial.polynomial.polyval(X[1] / 1e4, cz)
+
+    I = ex.to_reference(torch.tensor(f(mc)[None]), rc, kc, 8, 4, "gauss")
+    np.testing.assert_allclose(I.numpy()[0], f(mf), rtol=0, atol=1e-12 * np.abs(f(mf)).max())
+    # the Gauss rule of k+1 points integrates degree 2k+1 exactly
+    F = torch.tensor((synth.node_coords(mf)[0] / 3e5) ** 4 * (synth.node_coords(mf)[1] / 1e4) ** 4)[None]
+    assert float(ex.l2_sq(F, 8, 4, "gauss")[0]) == pytest.approx(3e5 * 1e4 / 81.0, rel=1e-12)

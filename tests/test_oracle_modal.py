@@ -154,4 +154,5 @@ def test_sponge_by_projection_keeps_total_density():
         np.testing.assert_allclose(U1[v, below], c.U[v, below], rtol=0,
                                    atol=1e-13 * np.abs(c.U[v]).max())
     above = ez == 3
-    assert np.all(np.abs(U1[3:6, above]).sum() < 0.9 * np.abs(c.U[3:6, above]).sum())
+    for v in range(1, 7):                                  # rho_m', rho_r', m, E' relax
+        assert np.abs(U1[v, above]).sum() < 0.9 * np.abs(c.U[v, above]).sum(), v
