@@ -29,7 +29,8 @@ class OraParams(ct.Structure):
     _fields_ = [(n, ct.c_double) for n in
                 ("g", "cvd", "cvv", "cl", "cpd", "cpv", "Rd", "Rv", "Lref", "Tref", "eref", "pref")] + \
                [("rain", ct.c_int), ("vr_mode", ct.c_int)] + \
-               [(n, ct.c_double) for n in ("vr_const", "rho_w", "N0r", "v0r", "q_au", "sponge_zD", "sponge_alpha")]
+               [(n, ct.c_double) for n in ("vr_const", "rho_w", "N0r", "v0r", "q_au", "sponge_zD", "sponge_alpha",
+                                           "sip_gamma", "sip_sigma")]
 
 
 class OraMesh(ct.Structure):
@@ -54,6 +55,7 @@ def lib():
         L.ora_tables.argtypes = [ct.c_int, dp, dp, dp, dp]
         L.ora_gauss_tables.argtypes = [ct.c_int, dp, dp]
         L.ora_project.argtypes = [ct.c_void_p, dp, dp]
+        L.ora_sip.argtypes = [ct.c_void_p, dp, dp, dp]
         L.ora_esat.argtypes = [ct.POINTER(OraParams), ct.c_double]
         L.ora_esat.restype = ct.c_double
         L.ora_rho_vs.argtypes = [ct.POINTER(OraParams), ct.c_double]
@@ -231,6 +233,16 @@ class Oracle:
         Fs = np.zeros(self.nvars)
         lib().ora_face(self.h, _p(Um), izm, _p(Up), izp, j, _p(Fs))
         return Fs
+
+    def sip(self, U: np.ndarray, W: Optional[np.ndarray] = None) -> np.ndarray:
+        """-M^{-1} A_h(U, .), the artificial diffusion alone, with the viscosity of W's velocity
+        (W = U if not given)."""
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        W = U if W is None else np.ascontiguousarray(W, dtype=np.float64)
+        out = np.zeros_like(U)
+        if lib().ora_sip(self.h, _p(U), _p(W), _p(out)) != 0:
+            raise ValueError("needs the Lobatto basis and sip_gamma > 0")
+        return out
 
     def project(self, U: np.ndarray) -> np.ndarray:
         """Legendre coefficients of a state given at the Gauss points (modal basis)."""

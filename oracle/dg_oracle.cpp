@@ -109,6 +109,9 @@ struct OraParams {
   // Rayleigh sponge (Section 3.6): bottom height z_D and
   // strength alpha of the blending function; alpha = 0 switches it off
   double sponge_zD, sponge_alpha;
+  // artificial diffusion (Section 3.5): viscosity scale gamma (0: off) and
+  // penalty sigma of the symmetric interior penalty form
+  double sip_gamma, sip_sigma;
 };
 
 struct OraMesh {
@@ -130,6 +133,7 @@ void ora_default_params(OraParams* p) {
   // COSMO warm-rain distribution parameters (Section 2.1)
   p->rho_w = 1000.0; p->N0r = 8.0e6; p->v0r = 130.0; p->q_au = 0.0;
   p->sponge_zD = 0.0; p->sponge_alpha = 0.0;
+  p->sip_gamma = 0.0; p->sip_sigma = 10.0;
 }
 
 }  // extern "C"
@@ -518,6 +522,158 @@ template <class R> void ghost_state(const Ctx& c, const R* Ua, int j, R* Ug) {
 }
 
 // dU/dt = M^{-1} [ (F, grad V)_K - sum_faces (F_n, [V]) + (G, V)_K ] on every node.
+// ---------------------------------------------------------------------------
+// artificial diffusion (Section 3.5), Lobatto basis: the symmetric interior
+// penalty form on the interior faces
+//   A_h(U, V) = sum_K (alpha grad U, grad V)_K
+//             + sum_F [ -(alpha {grad U}.n, [V])_F - (alpha {grad V}.n, [U])_F
+//                       + sigma k^2 / h_n (alpha [U], [V])_F ]
+// acting on the perturbation unknowns, with the element-wise viscosity
+//   alpha_K = gamma 0.5 h^(1 - d/2) ||u||_{0,K}   (||u - v_r e_z||_{0,K} for rho_r),
+// h = |K|^(1/d), carried to a continuous Q1 field by the mean over the
+// elements that share each vertex.  Slip walls carry no diffusive terms.
+// ---------------------------------------------------------------------------
+double elem_h(const Ctx& c) {
+  double v = 1.0;
+  for (int a = 0; a < c.d; ++a) v *= c.h[a];
+  return std::pow(v, 1.0 / c.d);
+}
+
+// nodal viscosity from the velocities of the points q: an[0] for every
+// variable but rho_r, an[1] for rho_r
+template <class R> void sip_alpha(const Ctx& c, const std::vector<Point<R>>& q, std::vector<double>* an) {
+  const int ne = c.ne, np = c.np, d = c.d, p1 = c.k + 1;
+  double J = 1.0;
+  for (int a = 0; a < d; ++a) J *= 0.5 * c.h[a];
+  const double pre = c.P.sip_gamma * 0.5 * std::pow(elem_h(c), 1.0 - 0.5 * d);
+  std::vector<double> aK[2] = {std::vector<double>(ne), std::vector<double>(ne)};
+  for (int e = 0; e < ne; ++e) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int n = 0; n < np; ++n) {
+      double w = J;
+      for (int a = 0; a < d; ++a) w *= c.tab.w[node_axis(n, a, p1)];
+      const Point<R>& qq = q[(long)e * np + n];
+      double u2 = 0.0, ur2 = 0.0;
+      for (int i = 0; i < d; ++i) {
+        const double ui = val(qq.u[i]);
+        const double ur = (i == d - 1) ? ui - val(qq.vr) : ui;
+        u2 += ui * ui;
+        ur2 += ur * ur;
+      }
+      s0 += w * u2;
+      s1 += w * ur2;
+    }
+    aK[0][e] = pre * std::sqrt(s0);
+    aK[1][e] = pre * std::sqrt(s1);
+  }
+  // vertex means; a periodic axis has n vertices, a walled one n + 1
+  int nvx[3] = {1, 1, 1};
+  for (int a = 0; a < d; ++a) nvx[a] = c.M.n[a] + (c.M.bc[a] == 0 ? 0 : 1);
+  const int nvert = nvx[0] * nvx[1] * nvx[2];
+  std::vector<double> vs[2] = {std::vector<double>(nvert, 0.0), std::vector<double>(nvert, 0.0)};
+  std::vector<int> cnt(nvert, 0);
+  auto vid = [&](int e, int corner) {
+    int id = 0, stride = 1;
+    for (int a = 0; a < d; ++a) {
+      int va = elem_axis(c, e, a) + ((corner >> a) & 1);
+      if (c.M.bc[a] == 0) va %= c.M.n[a];
+      id += va * stride;
+      stride *= nvx[a];
+    }
+    return id;
+  };
+  for (int e = 0; e < ne; ++e)
+    for (int corner = 0; corner < (1 << d); ++corner) {
+      const int id = vid(e, corner);
+      vs[0][id] += aK[0][e];
+      vs[1][id] += aK[1][e];
+      cnt[id] += 1;
+    }
+  for (int f = 0; f < 2; ++f) an[f].assign((size_t)ne * np, 0.0);
+  for (int e = 0; e < ne; ++e)
+    for (int n = 0; n < np; ++n)
+      for (int corner = 0; corner < (1 << d); ++corner) {
+        double wq = 1.0;
+        for (int a = 0; a < d; ++a) {
+          const double xi = c.tab.x[node_axis(n, a, p1)];
+          wq *= ((corner >> a) & 1) ? 0.5 * (1.0 + xi) : 0.5 * (1.0 - xi);
+        }
+        const int id = vid(e, corner);
+        for (int f = 0; f < 2; ++f) an[f][(long)e * np + n] += wq * vs[f][id] / cnt[id];
+      }
+}
+
+// dU -= M^{-1} A_h(U, .): for every nodal basis function phi_i, A_h(U, phi_i)
+// evaluated on the support of phi_i (its element and that element's faces)
+template <class R> void sip_add(const Ctx& c, const R* U, R* dU, const std::vector<double>* an) {
+  const int nv = c.nvars, np = c.np, ne = c.ne, d = c.d, k = c.k, p1 = k + 1;
+  const long N = (long)ne * np;
+  auto at = [&](int v, int e, int n) -> long { return (long)v * N + (long)e * np + n; };
+  double J = 1.0;
+  for (int a = 0; a < d; ++a) J *= 0.5 * c.h[a];
+  const Tables& t = c.tab;
+  // gradient of every variable at every node
+  std::vector<R> G((size_t)d * nv * N);
+  auto g_at = [&](int j, int v, int e, int n) -> R& { return G[((size_t)j * nv + v) * N + (long)e * np + n]; };
+  for (int j = 0; j < d; ++j)
+    for (int v = 0; v < nv; ++v)
+      for (int e = 0; e < ne; ++e)
+        for (int n = 0; n < np; ++n) {
+          const int a = node_axis(n, j, p1);
+          R sacc = R(0.0);
+          for (int b = 0; b < p1; ++b) sacc += t.D[a * p1 + b] * U[at(v, e, node_set_axis(n, j, b, p1))];
+          g_at(j, v, e, n) = (2.0 / c.h[j]) * sacc;
+        }
+  // d/dx_j phi_i at node q of the same element
+  auto dphi = [&](int i, int q, int j) -> double {
+    for (int a = 0; a < d; ++a)
+      if (a != j && node_axis(i, a, p1) != node_axis(q, a, p1)) return 0.0;
+    return (2.0 / c.h[j]) * t.D[node_axis(q, j, p1) * p1 + node_axis(i, j, p1)];
+  };
+  const double sig = c.P.sip_sigma * k * k;
+  for (int e = 0; e < ne; ++e)
+    for (int i = 0; i < np; ++i)
+      for (int v = 0; v < nv; ++v) {
+        const std::vector<double>& al = an[(c.P.rain && v == v_rr(c)) ? 1 : 0];
+        R A = R(0.0);
+        // volume
+        for (int q = 0; q < np; ++q) {
+          double wq = J;
+          for (int a = 0; a < d; ++a) wq *= t.w[node_axis(q, a, p1)];
+          for (int j = 0; j < d; ++j) {
+            const double dp = dphi(i, q, j);
+            if (dp != 0.0) A += (wq * al[(long)e * np + q] * dp) * g_at(j, v, e, q);
+          }
+        }
+        // faces of e, normal +e_j from the lower to the upper element
+        for (int j = 0; j < d; ++j)
+          for (int side = 0; side < 2; ++side) {
+            const int ej = elem_axis(c, e, j);
+            const bool at_end = side ? ej == c.M.n[j] - 1 : ej == 0;
+            if (at_end && c.M.bc[j] == 1) continue;
+            const int e2 = elem_shift(c, e, j, side ? +1 : -1);
+            for (int nf = 0; nf < np; ++nf) {
+              if (node_axis(nf, j, p1) != (side ? k : 0)) continue;
+              const int nf2 = node_set_axis(nf, j, side ? 0 : k, p1);
+              double wf = 1.0;
+              for (int a = 0; a < d; ++a)
+                if (a != j) wf *= t.w[node_axis(nf, a, p1)] * 0.5 * c.h[a];
+              const R Ue = U[at(v, e, nf)], Uo = U[at(v, e2, nf2)];
+              const R jumpU = side ? Ue - Uo : Uo - Ue;
+              const R avgG = 0.5 * (g_at(j, v, e, nf) + g_at(j, v, e2, nf2));
+              const double phi = (i == nf) ? 1.0 : 0.0;
+              const double jumpPhi = side ? phi : -phi;
+              const double avgPhi = 0.5 * dphi(i, nf, j);
+              const double alf = al[(long)e * np + nf];
+              A += wf * alf * (-(avgG * jumpPhi) - avgPhi * jumpU + (sig / c.h[j]) * jumpU * jumpPhi);
+            }
+          }
+        double wi = J;
+        for (int a = 0; a < d; ++a) wi *= t.w[node_axis(i, a, p1)];
+        dU[at(v, e, i)] -= A / wi;
+      }
+}
+
 template <class R> void rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
   const int nv = c.nvars, np = c.np, ne = c.ne, d = c.d, k = c.k, p1 = k + 1;
   const long N = (long)ne * np;
@@ -602,6 +758,12 @@ template <class R> void rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
   for (int e = 0; e < ne; ++e)
     for (int n = 0; n < np; ++n)
       for (int v = 0; v < nv; ++v) dU[at(v, e, n)] += q[(long)e * np + n].G[v];
+  // 5. artificial diffusion
+  if (c.P.sip_gamma > 0.0) {
+    std::vector<double> an[2];
+    sip_alpha(c, q, an);
+    sip_add(c, U, dU, an);
+  }
   if (wall_rain_flux) *wall_rain_flux = wflux;
 }
 
@@ -981,6 +1143,7 @@ void* ora_create(const OraMesh* M, const OraParams* P, int nvars, const double* 
                  const double* rm, const double* rr, const double* E) {
   if (M->dim < 2 || M->dim > 3 || M->order < 1 || M->order > 8) return nullptr;
   if (M->basis != 0 && M->basis != 1) return nullptr;
+  if (M->basis == 1 && P->sip_gamma > 0.0) return nullptr;   // diffusion: Lobatto basis only
   if (nvars != (P->rain ? 4 : 3) + M->dim) return nullptr;
   Ctx* c = new Ctx();
   c->M = *M; c->P = *P;
@@ -1192,6 +1355,26 @@ void ora_face(void* h, const double* Um, int izm, const double* Up, int izp, int
   pointwise(*c, Um, izm, a);
   pointwise(*c, Up, izp, b);
   lf_flux(*c, a, Um, b, Up, j, Fs);
+}
+
+// The diffusive term alone, -M^{-1} A_h(U, .), with the viscosity taken from
+// the velocities of the state W (Lobatto basis, sip_gamma > 0)
+int ora_sip(void* h, const double* U, const double* W, double* out) {
+  Ctx* c = (Ctx*)h;
+  if (c->basis != 0 || !(c->P.sip_gamma > 0.0)) return -1;
+  const long N = (long)c->ne * c->np;
+  std::vector<Point<double>> q(N);
+  std::vector<double> Wq(c->nvars);
+  for (int e = 0; e < c->ne; ++e)
+    for (int n = 0; n < c->np; ++n) {
+      for (int v = 0; v < c->nvars; ++v) Wq[v] = W[(long)v * N + (long)e * c->np + n];
+      pointwise(*c, Wq.data(), height_of(*c, e, n), q[(long)e * c->np + n]);
+    }
+  std::vector<double> an[2];
+  sip_alpha(*c, q, an);
+  std::fill(out, out + N * c->nvars, 0.0);
+  sip_add(*c, U, out, an);
+  return 0;
 }
 
 // Legendre coefficients (the L2 projection by the Gauss rule) of a state given
