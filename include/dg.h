@@ -115,6 +115,18 @@ typedef struct {
    * dg_rk_step_vjp return DG_EUNSUPPORTED, and dg_reduce_mass leaves its
    * wall-flux entry NaN. */
   int basis;                  /* DG_BASIS_LOBATTO or DG_BASIS_GAUSS             */
+  /* Artificial diffusion (Section 3.5), Lobatto basis only: the symmetric
+   * interior penalty form on interior faces, with penalty
+   * sip_sigma k^2 / h_n (the printed h^2/k is read as the usual k^2/h),
+   * acting on the perturbation unknowns.  The viscosity is
+   * sip_gamma 0.5 h^(1-d/2) ||u||_{0,K} per element (||u - v_r e_z||_{0,K}
+   * for rho_r), h = |K|^(1/d), evaluated from every stage state, and carried
+   * to a continuous Q1 field by vertex means.  Slip walls carry no
+   * diffusive terms.  sip_gamma = 0 (default) switches it off.  With it
+   * on, the adjoint calls return DG_EUNSUPPORTED, and so does dg_create*
+   * with DG_BASIS_GAUSS. */
+  double sip_gamma;           /* >= 0                                           */
+  double sip_sigma;           /* > 0 (default 10)                               */
 } dg_params;
 
 typedef struct {

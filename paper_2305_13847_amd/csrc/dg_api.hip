@@ -71,6 +71,11 @@ struct dg_handle {
   void* stage_w = nullptr;       // adjoint of the step's end state through the sponge
   double* sponge_d = nullptr;    // sponge blending factor per vertical node index
   double* bgf_d = nullptr;       // Gauss basis: background traces on horizontal faces
+  bool sip = false;              // artificial diffusion on
+  double* sip_aK = nullptr;      // per-element viscosity, two fields
+  double* sip_av = nullptr;      // vertex means, two fields
+  void* sip_out = nullptr;       // diffusive tendency (state layout)
+  std::vector<long long> nvert;  // vertices of each member
   bool sponge = false;
   double* auxT = nullptr;
   double* auxS = nullptr;
@@ -152,6 +157,7 @@ extern "C" void dg_default_params(dg_params* p) {
   p->precision = DG_FP64; p->rk = DG_SSPRK43;
   p->newton_rtol = 1e-14; p->newton_maxit = 30;
   p->basis = DG_BASIS_LOBATTO;
+  p->sip_gamma = 0.0; p->sip_sigma = 10.0;
 }
 
 // Lobatto nodes in closed form (k <= 4), weights 2 / (k (k+1) P_k(x)^2) and the
@@ -176,7 +182,7 @@ static void lobatto_nodes(int k, double* x) {
   }
 }
 
-static void lobatto_tables(int k, double* w, double* Dhat) {
+static void lobatto_tables(int k, double* w, double* Dhat, double* Dout = nullptr) {
   double x[kMaxP1];
   lobatto_nodes(k, x);
   const int p1 = k + 1;
@@ -195,6 +201,9 @@ static void lobatto_tables(int k, double* w, double* Dhat) {
     }
   for (int i = 0; i < p1; ++i)
     for (int a = 0; a < p1; ++a) Dhat[i * p1 + a] = w[a] * Dm[a][i] / w[i];
+  if (Dout)
+    for (int a = 0; a < p1; ++a)
+      for (int i = 0; i < p1; ++i) Dout[a * p1 + i] = Dm[a][i];
 }
 
 // Gauss-Legendre nodes and weights of the (k+1)-point rule in closed form
@@ -260,6 +269,7 @@ static void free_all(dg_handle* h) {
   for (auto& b : h->stage) F(b);
   for (auto& b : h->stage_x) F(b);
   F(h->stage_w); F(h->sponge_d); F(h->bgf_d);
+  F(h->sip_aK); F(h->sip_av); F(h->sip_out);
   F(h->auxT); F(h->auxS); F(h->auxT2); F(h->auxS2);
   F(h->auxT3); F(h->auxS3); F(h->auxT4); F(h->auxS4);
   F(h->dt_d); F(h->partial); F(h->red_out); F(h->stats);
@@ -345,6 +355,10 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   if (p->vr_mode != DG_VR_CONST && p->vr_mode != DG_VR_COSMO) return fail(DG_EINVAL, "bad vr_mode");
   if (!(p->newton_rtol > 0) || p->newton_maxit < 1) return fail(DG_EINVAL, "bad Newton settings");
   if (p->basis != DG_BASIS_LOBATTO && p->basis != DG_BASIS_GAUSS) return fail(DG_EINVAL, "bad basis");
+  if (!(p->sip_gamma >= 0.0) || !std::isfinite(p->sip_gamma) || !(p->sip_sigma > 0.0) || !std::isfinite(p->sip_sigma))
+    return fail(DG_EINVAL, "sip_gamma must be >= 0 and sip_sigma > 0");
+  if (p->sip_gamma > 0.0 && p->basis != DG_BASIS_LOBATTO)
+    return fail(DG_EUNSUPPORTED, "artificial diffusion exists for the Lobatto basis only");
   if (!(p->sponge_alpha >= 0.0 && p->sponge_alpha <= 1.0) || !std::isfinite(p->sponge_zD))
     return fail(DG_EINVAL, "sponge_alpha must lie in [0, 1] and sponge_zD be finite");
   if (p->sponge_alpha > 0.0)
@@ -380,6 +394,20 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
       md.lift[a][1] = md.two_over_h[a] / wq[order];
       if (a < dim) { ne *= g.n[a]; md.J *= 0.5 * hh; }
     }
+    {
+      double vol = 1.0;
+      for (int a = 0; a < dim; ++a) vol *= (g.hi[a] - g.lo[a]) / g.n[a];
+      const double hgeo = std::pow(vol, 1.0 / dim);
+      md.sip_pre = p->sip_gamma * 0.5 * std::pow(hgeo, 1.0 - 0.5 * dim);
+      long long nvm = 1;
+      for (int a = 0; a < 3; ++a) {
+        md.nvx[a] = a < dim ? g.n[a] + (g.bc[a] == DG_PERIODIC ? 0 : 1) : 1;
+        md.sip_tau[a] = a < dim ? p->sip_sigma * order * order * g.n[a] / (g.hi[a] - g.lo[a]) : 0.0;
+        nvm *= md.nvx[a];
+      }
+      md.voff = 0;   // set once every member's vertex count is known
+      h->nvert.push_back(nvm);
+    }
     for (int a = 0; a < dim; ++a) {
       md.face_J[a] = 1.0;
       for (int b = 0; b < dim; ++b)
@@ -396,6 +424,11 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
     h->mem.push_back(md);
   }
   h->hoff.push_back(hoff);
+  long long nvert_tot = 0;
+  for (int m = 0; m < nmembers; ++m) {
+    h->mem[m].voff = nvert_tot;
+    nvert_tot += h->nvert[m];
+  }
   build_items(h, epb);
   h->items_cap = items_max;
   {
@@ -438,6 +471,12 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
     ok = ok && A((void**)&h->sponge_d, sizeof(double) * hoff);
   }
   if (p->basis == DG_BASIS_GAUSS) ok = ok && A((void**)&h->bgf_d, sizeof(double) * 5 * 2 * (hoff / p1));
+  h->sip = p->sip_gamma > 0.0;
+  if (h->sip) {
+    ok = ok && A((void**)&h->sip_aK, sizeof(double) * 2 * eoff);
+    ok = ok && A((void**)&h->sip_av, sizeof(double) * 2 * nvert_tot);
+    ok = ok && A(&h->sip_out, h->state_bytes);
+  }
   ok = ok && A((void**)&h->dt_d, sizeof(double) * nmembers);
   ok = ok && A((void**)&h->partial, sizeof(double) * 3 * h->items_cap);
   ok = ok && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) == hipSuccess;
@@ -487,11 +526,16 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
     a.bgf = h->bgf_d;
     a.bgf_n = 2 * (hoff / p1);
   } else {
-    lobatto_tables(order, a.w, a.Dhat);
+    lobatto_tables(order, a.w, a.Dhat, a.Dm);
     lobatto_nodes(order, xnode);
+    for (int i = 0; i <= order; ++i) a.xn[i] = xnode[i];
     a.bgf = nullptr;
     a.bgf_n = 0;
   }
+  a.sip_aK = h->sip_aK;
+  a.sip_av = h->sip_av;
+  a.sip_out = h->sip_out;
+  a.nvert = nvert_tot;
   a.mem = h->mem_d;
   a.items = h->items_d;
   a.nitems = (int)h->items.size();
@@ -664,13 +708,24 @@ static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, cons
                             c0, c1, c2, oT, oS, flags, s);
 }
 
+// artificial diffusion of the state U into the handle's tendency buffer
+static void do_sip(dg_handle* h, const void* U, hipStream_t s) {
+  KTimer kt(h, DG_K_OTHER, s);
+  const LaunchCfg lc = launch_cfg(h);
+  if (h->prec == DG_FP64)
+    Launch<double>::sip(h->ka, lc, h->order, h->dim, h->rain, h->nmembers, h->nvert.data(), U, s);
+  else
+    Launch<float>::sip(h->ka, lc, h->order, h->dim, h->rain, h->nmembers, h->nvert.data(), U, s);
+}
+
 extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t s) {
   dg_status st = ready(h);
   if (st != DG_OK) return st;
   if (!U || !dUdt) return fail(DG_EINVAL, "null state pointer");
   if (U == dUdt) return fail(DG_EINVAL, "U and dUdt must not alias");
   if (!do_split(h, U, nullptr, h->auxT, h->auxS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
-  do_rhs(h, 0, U, h->auxT, h->auxS, dUdt, nullptr, 0, 0, 0, s);
+  if (h->sip) do_sip(h, U, s);
+  do_rhs(h, 0, U, h->auxT, h->auxS, dUdt, nullptr, 0, 0, 0, s, nullptr, nullptr, h->sip ? kSip : 0);
   HIP_TRY(hipGetLastError());
   return DG_OK;
 }
@@ -727,7 +782,9 @@ static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t
     // the last stage of every fourth step so series updates never chain long;
     // the last stage ends the step and applies the sponge
     const bool last = st == ns - 1;
-    const int flags = (last && (step & 3) == 3 ? kRefreshRvs : 0) | (last && h->sponge ? kSponge : 0);
+    const int flags = (last && (step & 3) == 3 ? kRefreshRvs : 0) | (last && h->sponge ? kSponge : 0) |
+                      (h->sip ? kSip : 0);
+    if (h->sip) do_sip(h, in, s);
     do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], flags);
     *cur = b;
   }
@@ -826,7 +883,8 @@ static bool do_vjp(dg_handle* h, const void* U, const double* aT, const double* 
 extern "C" dg_status dg_rhs_vjp(dg_handle* h, const void* U, const void* lam, void* Ub, hipStream_t s) {
   dg_status st = ready(h);
   if (st != DG_OK) return st;
-  if (h->P.basis != DG_BASIS_LOBATTO) return fail(DG_EUNSUPPORTED, "adjoints exist for the Lobatto basis only");
+  if (h->P.basis != DG_BASIS_LOBATTO || h->sip)
+    return fail(DG_EUNSUPPORTED, "adjoints exist for the Lobatto basis without diffusion only");
   if (!U || !lam || !Ub) return fail(DG_EINVAL, "null pointer");
   if (Ub == U || Ub == lam) return fail(DG_EINVAL, "U_bar must not alias U or dUdt_bar");
   if (!do_split(h, U, nullptr, h->auxT, h->auxS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
@@ -866,7 +924,8 @@ extern "C" dg_status dg_rk_step_vjp(dg_handle* h, const void* Un, const void* W,
                                     hipStream_t s) {
   dg_status st = ready(h);
   if (st != DG_OK) return st;
-  if (h->P.basis != DG_BASIS_LOBATTO) return fail(DG_EUNSUPPORTED, "adjoints exist for the Lobatto basis only");
+  if (h->P.basis != DG_BASIS_LOBATTO || h->sip)
+    return fail(DG_EUNSUPPORTED, "adjoints exist for the Lobatto basis without diffusion only");
   if (!Un || !W || !Ub0 || !dt) return fail(DG_EINVAL, "null pointer");
   if (Ub0 == Un || Ub0 == W) return fail(DG_EINVAL, "U_n_bar must not alias U_n or U_np1_bar");
   st = upload_dt(h, dt, s);

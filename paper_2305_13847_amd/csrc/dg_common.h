@@ -21,6 +21,12 @@ struct MemberDesc {
   long long eoff;       // first global element
   int ne;               // elements of this member
   int hoff;             // first background index (n_z (k+1) entries)
+  // artificial diffusion: gamma 0.5 h^(1-d/2), the penalty sigma k^2 / h_j,
+  // the vertices per axis and the first vertex of this member
+  double sip_pre;
+  double sip_tau[3];
+  int nvx[3];
+  long long voff;
 };
 
 // A work item: EPB consecutive elements of one member, starting at element e0
@@ -56,6 +62,15 @@ struct KArgs {
   // concatenated columns (hoff / (k+1) + ez) and side s (0 bottom, 1 top)
   const double* bgf;
   int bgf_n;
+  // artificial diffusion (Lobatto basis): collocation derivative matrix
+  // Dm[a*(k+1)+i] = l_i'(x_a), Lobatto nodes, per-element viscosity aK[2][e],
+  // vertex means av[2][vertex] and the diffusive tendency (state layout)
+  double Dm[kMaxP1 * kMaxP1];
+  double xn[kMaxP1];
+  double* sip_aK;
+  double* sip_av;
+  void* sip_out;
+  long long nvert;
   // members and work items (member, first element) of EPB elements each
   const MemberDesc* mem;
   const Item* items;

@@ -73,6 +73,8 @@ __host__ __device__ inline int grid_for_items(int nitems) { return ((nitems + 7)
 // flags of a stage launch
 constexpr int kRefreshRvs = 1;   // store a fresh rho_vs(T) evaluation (anchors later splits)
 constexpr int kSponge = 2;       // the stage ends a time step: apply the sponge
+// the diffusive tendency in a.sip_out is added to the right-hand side
+constexpr int kSip = 4;
 
 // The sponge at the end of a step (Section 3.6):
 // (rho_m', rho_r', m, E') <- (1 - delta) (rho_m', rho_r', m, E') with the
@@ -589,6 +591,10 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
     R Us[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) Us[v] = sU[v * NT + t];
+    if (flags & kSip) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Rv[v] += ld((const R*)a.sip_out, N, v, g);
+    }
     stage_epilogue<R, D, RAIN, MODE>(a, bg, iz, g, N, Us, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS, flags,
                                      iters, bad);
   }
@@ -665,6 +671,10 @@ __device__ __forceinline__ void rhs_item(const KArgs& a, int it_, R (*sF)[Vars<D
   int iters = 0, bad = 0;
   if (active) {
     sources<R, D, RAIN>(a, Uq, q, Rv);
+    if (flags & kSip) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Rv[v] += (((const R*)a.sip_out) + (size_t)v * N)[g];
+    }
     if (MODE == 0) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) (out + (size_t)v * N)[g] = Rv[v];

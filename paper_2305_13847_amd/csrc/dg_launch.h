@@ -4,6 +4,7 @@
 #include <type_traits>
 #include "dg_kernels.h"
 #include "dg_gauss.h"
+#include "dg_sip.h"
 #include "dg_vjp.h"
 
 namespace dgm {
@@ -87,6 +88,20 @@ struct Launch {
         hipLaunchKernelGGL((rhs_kernel_persistent<R, K_, D_, R_, 2>), grid, block, 0, s, a, a_dev, (const R*)U,
                            auxT, auxS, (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, flags);
 #undef DGM_RHS
+    });
+  }
+
+  // artificial diffusion: alpha_K, vertex means (per member), tendency
+  static bool sip(const KArgs& a, LaunchCfg lc, int K, int D, int rain, int nmembers, const long long* nvert,
+                  const void* U, hipStream_t s) {
+    return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
+      constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
+      hipLaunchKernelGGL((sip_alpha_kernel<R, K_, D_, R_>), dim3(lc.grid), dim3(lc.threads), 0, s, a,
+                         (const R*)U);
+      for (int m = 0; m < nmembers; ++m)
+        hipLaunchKernelGGL((sip_vertex_kernel<D_>), dim3((unsigned)((nvert[m] + 127) / 128)), dim3(128), 0, s,
+                           a, m);
+      hipLaunchKernelGGL((sip_kernel<R, K_, D_, R_>), dim3(lc.grid), dim3(lc.threads), 0, s, a, (const R*)U);
     });
   }
 

@@ -1,0 +1,309 @@
+// Artificial diffusion (Section 3.5) on the Lobatto basis: the symmetric
+// interior penalty form on interior faces, acting on the perturbation
+// unknowns, with the element-wise viscosity
+//   alpha_K = gamma 0.5 h^(1-d/2) ||u||_{0,K}   (||u - v_r e_z||_{0,K} for rho_r)
+// carried to a continuous Q1 field by the mean over the elements that share
+// each vertex.  Three kernels per right-hand side:
+//   1. sip_alpha_kernel: alpha_K of every element (two fields), an LDS
+//      reduction over the element's nodes;
+//   2. sip_vertex_kernel: the vertex means;
+//   3. sip_kernel: the tendency S = -M^{-1} A_h(U, .) at every node, written
+//      in the state layout; the stage kernels add it to the right-hand side.
+// With nodes at the Lobatto points, S at node i reads (d_j = 2/h_j, D the
+// collocation derivative matrix, Dhat its weak form, G_j = d_j D U along the
+// j-line, alpha continuous):
+//   S_i = - sum_j d_j sum_a Dhat[i_j][a] (alpha G_j)_a
+//         + sum_j sum_{sides s} d_j / w_{i_j} alpha_f ( d_j/2 D[f_j][i_j] [U]_f
+//                                  + [i_j = f_j] s ({G_j}_f - tau_j [U]_f) )
+// where f is the face node of i's j-line on side s (s = -1 at xi_j = -1,
+// +1 at xi_j = +1), [U] = U(lower element) - U(upper element) across the
+// face, {G_j} the mean of both sides' gradients, tau_j = sigma k^2 / h_j.
+// Faces on slip walls contribute nothing.
+#pragma once
+#include "dg_kernels.h"
+
+namespace dgm {
+
+template <typename R, int K, int D, int RAIN>
+__global__ void __launch_bounds__(256)
+sip_alpha_kernel(KArgs a, const R* __restrict__ U) {
+  using S = Shape<K, D, block_threads<R>()>;
+  using V = Vars<D, RAIN>;
+  constexpr int P1 = S::P1, NP = S::NP, NT = S::NT;
+  __shared__ double sm[2][NT];
+  const ItemWalk walk(a.nitems);
+  for (int kk = 0;; ++kk) {
+    const int it_ = walk.item(kk);
+    if (it_ < 0) break;
+    const int t = threadIdx.x;
+    const Item item = a.items[it_];
+    const MemberDesc& md = a.mem[item.member];
+    const int le = t / NP, n = t - le * NP;
+    const int e = item.e0 + le;
+    double s0 = 0.0, s1 = 0.0;
+    if (e < md.ne) {
+      const unsigned N = a.nnodes;
+      const unsigned g = (unsigned)(md.eoff + e) * NP + n;
+      const ElemCoord<D> ec = item_coord<D>(md, item, le);
+      const int idx[3] = {n % P1, (n / P1) % P1, D == 3 ? n / (P1 * P1) : 0};
+      const int iz = md.hoff + ec.c[D - 1] * P1 + idx[D - 1];
+      const double rd = a.bg_rd[iz] + (double)ld(U, N, V::RD, g);
+      const double rm = a.bg_rm[iz] + (double)ld(U, N, V::RM, g);
+      const double rr = RAIN ? a.bg_rr[iz] + (double)ld(U, N, V::RR, g) : 0.0;
+      const double irho = 1.0 / (rd + rm + rr);
+      double w = md.J;
+#pragma unroll
+      for (int j = 0; j < D; ++j) w *= a.w[idx[j]];
+      double vr = 0.0;
+      if (RAIN) vr = a.vr_mode == 0 ? a.vr_const : (rr > 0.0 ? a.vr_pref * pow(rr, 0.125) : 0.0);
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const double ui = (double)ld(U, N, V::M0 + i, g) * irho;
+        const double ur = (i == D - 1) ? ui - vr : ui;
+        s0 += w * ui * ui;
+        s1 += w * ur * ur;
+      }
+    }
+    sm[0][t] = s0;
+    sm[1][t] = s1;
+    __syncthreads();
+    if (n == 0 && e < md.ne) {
+      double a0 = 0.0, a1 = 0.0;
+      for (int m = 0; m < NP; ++m) {
+        a0 += sm[0][le * NP + m];
+        a1 += sm[1][le * NP + m];
+      }
+      a.sip_aK[md.eoff + e] = md.sip_pre * sqrt(a0);
+      a.sip_aK[a.etot + md.eoff + e] = md.sip_pre * sqrt(a1);
+    }
+    __syncthreads();
+  }
+}
+
+// one thread per vertex of member m: the mean of alpha_K over the elements
+// that share it (a periodic axis wraps, a walled one has n + 1 vertices)
+template <int D>
+__global__ void sip_vertex_kernel(KArgs a, int m) {
+  const MemberDesc& md = a.mem[m];
+  const long long nv = (long long)md.nvx[0] * md.nvx[1] * md.nvx[2];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nv) return;
+  int v[3] = {(int)(i % md.nvx[0]), (int)((i / md.nvx[0]) % md.nvx[1]), (int)(i / ((long long)md.nvx[0] * md.nvx[1]))};
+  double s0 = 0.0, s1 = 0.0;
+  int cnt = 0;
+  for (int corner = 0; corner < (1 << D); ++corner) {
+    int c[3] = {0, 0, 0};
+    bool ok = true;
+    for (int ax = 0; ax < D; ++ax) {
+      int ca = v[ax] - ((corner >> ax) & 1);
+      if (md.bc[ax] == 0) {
+        if (ca < 0) ca += md.n[ax];
+      } else if (ca < 0 || ca >= md.n[ax]) {
+        ok = false;
+      }
+      c[ax] = ca;
+    }
+    if (!ok) continue;
+    const long long e = c[0] + (long long)md.n[0] * (c[1] + (long long)md.n[1] * c[2]);
+    s0 += a.sip_aK[md.eoff + e];
+    s1 += a.sip_aK[a.etot + md.eoff + e];
+    ++cnt;
+  }
+  a.sip_av[md.voff + i] = s0 / cnt;
+  a.sip_av[a.nvert + md.voff + i] = s1 / cnt;
+}
+
+template <typename R, int K, int D, int RAIN>
+__global__ void __launch_bounds__(256)
+sip_kernel(KArgs a, const R* __restrict__ U) {
+  using S = Shape<K, D, block_threads<R>()>;
+  using V = Vars<D, RAIN>;
+  constexpr int P1 = S::P1, NP = S::NP, NV = V::NV, NT = S::NT;
+  constexpr int NF = (D == 2) ? P1 : P1 * P1;          // nodes of one face
+  constexpr int NFE = 2 * D * NF;
+  constexpr int NFB = S::EPB * NFE;
+  __shared__ R sU[NV * NT];
+  __shared__ R sG[D * NV * NT];
+  __shared__ R sA[2 * NT];
+  __shared__ R sJ[NV * NFB];
+  __shared__ R sM[NV * NFB];
+  __shared__ R sDm[P1 * P1];
+  __shared__ R sDh[P1 * P1];
+  const int t = threadIdx.x;
+  if (t < P1 * P1) {
+    sDm[t] = (R)a.Dm[t];
+    sDh[t] = (R)a.Dhat[t];
+  }
+  R* out = (R*)a.sip_out;
+  const int epb = (int)blockDim.x / NP;
+  const ItemWalk walk(a.nitems);
+#pragma clang loop unroll(disable)
+  for (int kk = 0;; ++kk) {
+    const int it_ = walk.item(kk);
+    if (it_ < 0) break;
+    const Item item = a.items[it_];
+    const MemberDesc& md = a.mem[item.member];
+    const unsigned N = a.nnodes;
+    const int le = t / NP, n = t - le * NP;
+    const int e = item.e0 + le;
+    const bool active = e < md.ne;
+    const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
+    const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
+    const int idx[3] = {n % P1, (n / P1) % P1, D == 3 ? n / (P1 * P1) : 0};
+    // A. the state and the Q1 viscosity at the node
+    R al[2] = {R(0), R(0)};
+    if (active) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sU[v * NT + t] = ld(U, N, v, g);
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int corner = 0; corner < (1 << D); ++corner) {
+        double wq = 1.0;
+        long long vid = 0, stride = 1;
+#pragma unroll
+        for (int ax = 0; ax < D; ++ax) {
+          const int b = (corner >> ax) & 1;
+          const double xi = a.xn[idx[ax]];
+          wq *= b ? 0.5 * (1.0 + xi) : 0.5 * (1.0 - xi);
+          int va = ec.c[ax] + b;
+          if (md.bc[ax] == 0 && va == md.n[ax]) va = 0;
+          vid += va * stride;
+          stride *= md.nvx[ax];
+        }
+        a0 += wq * a.sip_av[md.voff + vid];
+        a1 += wq * a.sip_av[a.nvert + md.voff + vid];
+      }
+      al[0] = (R)a0;
+      al[1] = (R)a1;
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) sU[v * NT + t] = R(0);
+    }
+    sA[t] = al[0];
+    sA[NT + t] = al[1];
+    __syncthreads();
+    // B. gradients along each direction
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+      const int base = t - idx[j] * str;
+      const R dj = (R)md.two_over_h[j];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        R acc = R(0);
+#pragma unroll
+        for (int b = 0; b < P1; ++b) acc += sDm[idx[j] * P1 + b] * sU[v * NT + base + b * str];
+        sG[(j * NV + v) * NT + t] = dj * acc;
+      }
+    }
+    __syncthreads();
+    // C. face nodes: [U] and {G_j} across every interior face of the block
+    for (int task = t; task < epb * NFE; task += (int)blockDim.x) {
+      const int fle = task / NFE;
+      const int r = task - fle * NFE;
+      const int f = r / NF;
+      const int fp = r - f * NF;
+      const int j = f >> 1, side = f & 1;
+      R jU[NV], mG[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) { jU[v] = R(0); mG[v] = R(0); }
+      const int fe = item.e0 + fle;
+      if (fe < md.ne) {
+        const ElemCoord<D> fc = item_coord<D>(md, item, fle);
+        const int c = j == 0 ? fc.c[0] : (j == 1 ? fc.c[1] : fc.c[D - 1]);   // no dynamic private index
+        const bool at_end = side ? (c == md.n[j] - 1) : (c == 0);
+        if (!(at_end && md.bc[j] == 1)) {
+          int cn = side ? c + 1 : c - 1;
+          if (cn < 0) cn += md.n[j];
+          if (cn >= md.n[j]) cn -= md.n[j];
+          const int en = fe + (cn - c) * elem_stride(md, j);
+          // node of the line through face point fp at position 0 along j
+          // (fp enumerates the other axes, the lower one fastest)
+          int nf0;
+          if (D == 2) {
+            nf0 = (j == 0) ? fp * P1 : fp;
+          } else {
+            const int u = fp % P1, w2 = fp / P1;
+            nf0 = (j == 0) ? P1 * (u + P1 * w2) : (j == 1 ? u + P1 * P1 * w2 : u + P1 * w2);
+          }
+          const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+          const int nown = nf0 + (side ? K : 0) * str;       // own face node
+          const int fnb = side ? 0 : K;                      // the neighbour's, along j
+          const unsigned gn0 = (unsigned)(md.eoff + en) * NP + nf0;
+          const R dj = (R)md.two_over_h[j];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            R gnb = R(0), unb = R(0);
+#pragma unroll
+            for (int b = 0; b < P1; ++b) {
+              const R ub = ld(U, N, v, gn0 + b * str);
+              gnb += sDm[fnb * P1 + b] * ub;
+              if (b == fnb) unb = ub;
+            }
+            gnb *= dj;
+            const R uo = sU[v * NT + fle * NP + nown];
+            const R go = sG[(j * NV + v) * NT + fle * NP + nown];
+            jU[v] = side ? uo - unb : unb - uo;
+            mG[v] = R(0.5) * (go + gnb);
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        sJ[v * NFB + task] = jU[v];
+        sM[v * NFB + task] = mG[v];
+      }
+    }
+    __syncthreads();
+    // D. the tendency at every node
+    if (active) {
+      R Sv[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Sv[v] = R(0);
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+        const int base = t - idx[j] * str;
+        const R dj = (R)md.two_over_h[j];
+        // volume
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          const int f = (RAIN && v == V::RR) ? 1 : 0;
+          R acc = R(0);
+#pragma unroll
+          for (int b = 0; b < P1; ++b)
+            acc += sDh[idx[j] * P1 + b] * (sA[f * NT + base + b * str] * sG[(j * NV + v) * NT + base + b * str]);
+          Sv[v] -= dj * acc;
+        }
+        // faces: this node's line meets the minus face (side 0) and the plus face (side 1)
+        int fpj;
+        if (D == 2) fpj = (j == 0) ? idx[1] : idx[0];
+        else fpj = (j == 0) ? idx[1] + P1 * idx[2] : (j == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
+        const R kw = dj / (R)a.w[idx[j]];
+        const R tau = (R)md.sip_tau[j];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int fj = side ? K : 0;
+          const int task = le * NFE + (2 * j + side) * NF + fpj;
+          const int nf = base + fj * str;                    // the face node (a thread of this element)
+          const R sgn = side ? R(1) : R(-1);
+          const R dfi = R(0.5) * dj * sDm[fj * P1 + idx[j]];
+#pragma unroll
+          for (int v = 0; v < NV; ++v) {
+            const int f = (RAIN && v == V::RR) ? 1 : 0;
+            const R alf = sA[f * NT + nf];
+            const R ju = sJ[v * NFB + task];
+            R term = dfi * ju;
+            if (idx[j] == fj) term += sgn * (sM[v * NFB + task] - tau * ju);
+            Sv[v] += kw * alf * term;
+          }
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) st(out, N, v, g, Sv[v]);
+    }
+    __syncthreads();   // the tiles are reused by the next item
+  }
+}
+
+}  // namespace dgm

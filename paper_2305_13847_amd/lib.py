@@ -44,7 +44,8 @@ class dg_params(ct.Structure):
                 ("rho_w", ct.c_double), ("N0r", ct.c_double), ("v0r", ct.c_double),
                 ("q_au", ct.c_double), ("precision", ct.c_int), ("rk", ct.c_int),
                 ("newton_rtol", ct.c_double), ("newton_maxit", ct.c_int),
-                ("sponge_zD", ct.c_double), ("sponge_alpha", ct.c_double), ("basis", ct.c_int)]
+                ("sponge_zD", ct.c_double), ("sponge_alpha", ct.c_double), ("basis", ct.c_int),
+                ("sip_gamma", ct.c_double), ("sip_sigma", ct.c_double)]
 
 
 class dg_stats(ct.Structure):

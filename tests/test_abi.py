@@ -58,7 +58,7 @@ int main(void) {
   F(dg_mesh, dim) F(dg_mesh, n) F(dg_mesh, lo) F(dg_mesh, hi) F(dg_mesh, bc)
   F(dg_params, g) F(dg_params, pref) F(dg_params, rain) F(dg_params, vr_mode) F(dg_params, vr_const)
   F(dg_params, q_au) F(dg_params, precision) F(dg_params, rk) F(dg_params, newton_rtol)
-  F(dg_params, newton_maxit) F(dg_params, sponge_zD) F(dg_params, sponge_alpha) F(dg_params, basis)
+  F(dg_params, newton_maxit) F(dg_params, sponge_zD) F(dg_params, sponge_alpha) F(dg_params, basis) F(dg_params, sip_gamma) F(dg_params, sip_sigma)
   F(dg_stats, splits) F(dg_stats, nonconverged) F(dg_stats, max_iters) F(dg_stats, nonfinite)
   return 0;
 }
