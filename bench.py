@@ -10,9 +10,10 @@ stages / wall time) with the state resident in HBM.
 Also reported on the same line: the roofline of the dominant kernel (the fused
 stage kernel: algorithmic bytes per launch / its HIP-event-timed duration
 against 8 TB/s), the FP64 run of the same workload, the same FP32 workload
-with the Rayleigh sponge layer on, the 2D moist bubble (128 x 64, Q4) in FP64
-and FP32, the batched ensemble, and the FP64 CPU reference timed on a bounded
-sample of the 3D workload.
+with the Rayleigh sponge layer on, with the artificial diffusion on, and in
+the paper's Legendre/Gauss basis (FP32 and FP64), the 2D moist bubble
+(128 x 64, Q4) in FP64 and FP32, the batched ensemble, and the FP64 CPU
+reference timed on a bounded sample of the 3D workload.
 """
 from __future__ import annotations
 
@@ -71,7 +72,7 @@ def time_workload(case, precision, steps, warmup, lib, torch, kernel_timing=True
                dof_stage_per_s=dofs * 4 * steps / el,
                ms_per_step=1e3 * el / steps)
     if kernel_timing:
-        for name, k in (("stage", lib.DG_K_STAGE), ("split", lib.DG_K_SPLIT)):
+        for name, k in (("stage", lib.DG_K_STAGE), ("split", lib.DG_K_SPLIT), ("other", lib.DG_K_OTHER)):
             ms, n = dg.timing_read(k)
             out[name + "_us"] = 1e3 * ms / max(n, 1)
             out[name + "_launches"] = n
@@ -183,7 +184,21 @@ def main():
         rsp = time_workload(case, lib.DG_FP32_BULK, args.steps, args.warmup, lib, torch,
                             sponge_zD=7.0e3, sponge_alpha=0.5)
         extra["rain3d_fp32_sponge"] = {k: rsp[k] for k in ("dof_stage_per_s", "ms_per_step", "stage_us")}
+        # the same FP32 workload with the artificial diffusion (gamma 0.6, the
+        # paper's 3D value); its three kernels per stage are the "other" class
+        rsi = time_workload(case, lib.DG_FP32_BULK, args.steps, args.warmup, lib, torch, sip_gamma=0.6)
+        extra["rain3d_fp32_sip"] = {k: rsi[k] for k in ("dof_stage_per_s", "ms_per_step", "stage_us")}
+        extra["rain3d_fp32_sip"]["sip_us_per_stage"] = rsi["other_us"]
         del case
+        # the paper's own basis: Legendre modes with Gauss quadrature
+        case_g = synth.warm_rain_3d(basis="gauss")
+        for prec, nm, st in ((lib.DG_FP32_BULK, "rain3d_fp32_gauss", args.steps),
+                             (lib.DG_FP64, "rain3d_fp64_gauss", max(2, args.steps // 4))):
+            rg = time_workload(case_g, prec, st, 1, lib, torch)
+            sb = 4 if prec == lib.DG_FP32_BULK else 8
+            extra[nm] = {k: rg[k] for k in ("dof_stage_per_s", "ms_per_step", "stage_us")}
+            extra[nm]["roofline_frac"] = 2.25 * sb * nvars * nodes / (rg["stage_us"] * 1e-6) / 1e9 / HBM_PEAK_GBS
+        del case_g
         bub = synth.moist_bubble()
         for prec, nm in ((lib.DG_FP64, "bubble2d_q4_fp64"), (lib.DG_FP32_BULK, "bubble2d_q4_fp32")):
             r = time_workload(bub, prec, 50, 5, lib, torch)
