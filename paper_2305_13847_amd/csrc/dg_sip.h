@@ -67,14 +67,17 @@ sip_alpha_kernel(KArgs a, const R* __restrict__ U) {
     sm[0][t] = s0;
     sm[1][t] = s1;
     __syncthreads();
-    if (n == 0 && e < md.ne) {
-      double a0 = 0.0, a1 = 0.0;
-      for (int m = 0; m < NP; ++m) {
-        a0 += sm[0][le * NP + m];
-        a1 += sm[1][le * NP + m];
+    // fixed-order tree over the element's nodes
+    for (int h = 1; h < NP; h <<= 1) {
+      if ((n % (2 * h)) == 0 && n + h < NP) {
+        sm[0][t] += sm[0][t + h];
+        sm[1][t] += sm[1][t + h];
       }
-      a.sip_aK[md.eoff + e] = md.sip_pre * sqrt(a0);
-      a.sip_aK[a.etot + md.eoff + e] = md.sip_pre * sqrt(a1);
+      __syncthreads();
+    }
+    if (n == 0 && e < md.ne) {
+      a.sip_aK[md.eoff + e] = md.sip_pre * sqrt(sm[0][t]);
+      a.sip_aK[a.etot + md.eoff + e] = md.sip_pre * sqrt(sm[1][t]);
     }
     __syncthreads();
   }
@@ -129,6 +132,7 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
   __shared__ R sM[NV * NFB];
   __shared__ R sDm[P1 * P1];
   __shared__ R sDh[P1 * P1];
+  __shared__ double sV[2][S::EPB][1 << D];   // the viscosity at each element's corners
   const int t = threadIdx.x;
   if (t < P1 * P1) {
     sDm[t] = (R)a.Dm[t];
@@ -150,38 +154,46 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
     const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
     const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
     const int idx[3] = {n % P1, (n / P1) % P1, D == 3 ? n / (P1 * P1) : 0};
-    // A. the state and the Q1 viscosity at the node
-    R al[2] = {R(0), R(0)};
+    // A. the state, and the viscosity at the element's corners (vertex means)
     if (active) {
 #pragma unroll
       for (int v = 0; v < NV; ++v) sU[v * NT + t] = ld(U, N, v, g);
-      double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-      for (int corner = 0; corner < (1 << D); ++corner) {
-        double wq = 1.0;
+      if (n < (1 << D)) {
         long long vid = 0, stride = 1;
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) {
-          const int b = (corner >> ax) & 1;
-          const double xi = a.xn[idx[ax]];
-          wq *= b ? 0.5 * (1.0 + xi) : 0.5 * (1.0 - xi);
-          int va = ec.c[ax] + b;
+          int va = ec.c[ax] + ((n >> ax) & 1);
           if (md.bc[ax] == 0 && va == md.n[ax]) va = 0;
           vid += va * stride;
           stride *= md.nvx[ax];
         }
-        a0 += wq * a.sip_av[md.voff + vid];
-        a1 += wq * a.sip_av[a.nvert + md.voff + vid];
+        sV[0][le][n] = a.sip_av[md.voff + vid];
+        sV[1][le][n] = a.sip_av[a.nvert + md.voff + vid];
       }
-      al[0] = (R)a0;
-      al[1] = (R)a1;
     } else {
 #pragma unroll
       for (int v = 0; v < NV; ++v) sU[v * NT + t] = R(0);
     }
-    sA[t] = al[0];
-    sA[NT + t] = al[1];
     __syncthreads();
+    // the Q1 viscosity at the node
+    {
+      double a0 = 0.0, a1 = 0.0;
+      if (active) {
+#pragma unroll
+        for (int corner = 0; corner < (1 << D); ++corner) {
+          double wq = 1.0;
+#pragma unroll
+          for (int ax = 0; ax < D; ++ax) {
+            const double xi = a.xn[idx[ax]];
+            wq *= ((corner >> ax) & 1) ? 0.5 * (1.0 + xi) : 0.5 * (1.0 - xi);
+          }
+          a0 += wq * sV[0][le][corner];
+          a1 += wq * sV[1][le][corner];
+        }
+      }
+      sA[t] = (R)a0;
+      sA[NT + t] = (R)a1;
+    }
     // B. gradients along each direction
 #pragma unroll
     for (int j = 0; j < D; ++j) {
@@ -197,110 +209,98 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
       }
     }
     __syncthreads();
-    // C. face nodes: [U] and {G_j} across every interior face of the block
+    // C. face nodes: [U] and {G_j} across every interior face of the block,
+    // one variable at a time straight into LDS
     for (int task = t; task < epb * NFE; task += (int)blockDim.x) {
       const int fle = task / NFE;
       const int r = task - fle * NFE;
       const int f = r / NF;
       const int fp = r - f * NF;
       const int j = f >> 1, side = f & 1;
-      R jU[NV], mG[NV];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) { jU[v] = R(0); mG[v] = R(0); }
       const int fe = item.e0 + fle;
-      if (fe < md.ne) {
+      bool live = fe < md.ne;
+      int en = 0;
+      if (live) {
         const ElemCoord<D> fc = item_coord<D>(md, item, fle);
         const int c = j == 0 ? fc.c[0] : (j == 1 ? fc.c[1] : fc.c[D - 1]);   // no dynamic private index
         const bool at_end = side ? (c == md.n[j] - 1) : (c == 0);
-        if (!(at_end && md.bc[j] == 1)) {
-          int cn = side ? c + 1 : c - 1;
-          if (cn < 0) cn += md.n[j];
-          if (cn >= md.n[j]) cn -= md.n[j];
-          const int en = fe + (cn - c) * elem_stride(md, j);
-          // node of the line through face point fp at position 0 along j
-          // (fp enumerates the other axes, the lower one fastest)
-          int nf0;
-          if (D == 2) {
-            nf0 = (j == 0) ? fp * P1 : fp;
-          } else {
-            const int u = fp % P1, w2 = fp / P1;
-            nf0 = (j == 0) ? P1 * (u + P1 * w2) : (j == 1 ? u + P1 * P1 * w2 : u + P1 * w2);
-          }
-          const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
-          const int nown = nf0 + (side ? K : 0) * str;       // own face node
-          const int fnb = side ? 0 : K;                      // the neighbour's, along j
-          const unsigned gn0 = (unsigned)(md.eoff + en) * NP + nf0;
-          const R dj = (R)md.two_over_h[j];
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            R gnb = R(0), unb = R(0);
-#pragma unroll
-            for (int b = 0; b < P1; ++b) {
-              const R ub = ld(U, N, v, gn0 + b * str);
-              gnb += sDm[fnb * P1 + b] * ub;
-              if (b == fnb) unb = ub;
-            }
-            gnb *= dj;
-            const R uo = sU[v * NT + fle * NP + nown];
-            const R go = sG[(j * NV + v) * NT + fle * NP + nown];
-            jU[v] = side ? uo - unb : unb - uo;
-            mG[v] = R(0.5) * (go + gnb);
-          }
-        }
+        live = !(at_end && md.bc[j] == 1);
+        int cn = side ? c + 1 : c - 1;
+        if (cn < 0) cn += md.n[j];
+        if (cn >= md.n[j]) cn -= md.n[j];
+        en = fe + (cn - c) * elem_stride(md, j);
       }
+      // node of the line through face point fp at position 0 along j
+      // (fp enumerates the other axes, the lower one fastest)
+      int nf0;
+      if (D == 2) {
+        nf0 = (j == 0) ? fp * P1 : fp;
+      } else {
+        const int u = fp % P1, w2 = fp / P1;
+        nf0 = (j == 0) ? P1 * (u + P1 * w2) : (j == 1 ? u + P1 * P1 * w2 : u + P1 * w2);
+      }
+      const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+      const int nown = fle * NP + nf0 + (side ? K : 0) * str;   // own face node (LDS index)
+      const int fnb = side ? 0 : K;                             // the neighbour's, along j
+      const unsigned gn0 = (unsigned)(md.eoff + en) * NP + nf0;
+      const R dj = (R)md.two_over_h[j];
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
-        sJ[v * NFB + task] = jU[v];
-        sM[v * NFB + task] = mG[v];
+        R ju = R(0), mg = R(0);
+        if (live) {
+          R gnb = R(0), unb = R(0);
+#pragma unroll
+          for (int b = 0; b < P1; ++b) {
+            const R ub = ld(U, N, v, gn0 + b * str);
+            gnb += sDm[fnb * P1 + b] * ub;
+            if (b == fnb) unb = ub;
+          }
+          gnb *= dj;
+          const R uo = sU[v * NT + nown];
+          ju = side ? uo - unb : unb - uo;
+          mg = R(0.5) * (sG[(j * NV + v) * NT + nown] + gnb);
+        }
+        sJ[v * NFB + task] = ju;
+        sM[v * NFB + task] = mg;
       }
     }
     __syncthreads();
-    // D. the tendency at every node
+    // D. the tendency at every node, one variable at a time
     if (active) {
-      R Sv[NV];
+#pragma unroll 1
+      for (int v = 0; v < NV; ++v) {
+        const int fa = (RAIN && v == V::RR) ? 1 : 0;
+        R Sv = R(0);
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Sv[v] = R(0);
-#pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
-        const int base = t - idx[j] * str;
-        const R dj = (R)md.two_over_h[j];
-        // volume
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          const int f = (RAIN && v == V::RR) ? 1 : 0;
+        for (int j = 0; j < D; ++j) {
+          const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+          const int base = t - idx[j] * str;
+          const R dj = (R)md.two_over_h[j];
+          // volume
           R acc = R(0);
 #pragma unroll
           for (int b = 0; b < P1; ++b)
-            acc += sDh[idx[j] * P1 + b] * (sA[f * NT + base + b * str] * sG[(j * NV + v) * NT + base + b * str]);
-          Sv[v] -= dj * acc;
-        }
-        // faces: this node's line meets the minus face (side 0) and the plus face (side 1)
-        int fpj;
-        if (D == 2) fpj = (j == 0) ? idx[1] : idx[0];
-        else fpj = (j == 0) ? idx[1] + P1 * idx[2] : (j == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
-        const R kw = dj / (R)a.w[idx[j]];
-        const R tau = (R)md.sip_tau[j];
+            acc += sDh[idx[j] * P1 + b] * (sA[fa * NT + base + b * str] * sG[(j * NV + v) * NT + base + b * str]);
+          Sv -= dj * acc;
+          // faces: this node's line meets the minus face (side 0) and the plus face (side 1)
+          int fpj;
+          if (D == 2) fpj = (j == 0) ? idx[1] : idx[0];
+          else fpj = (j == 0) ? idx[1] + P1 * idx[2] : (j == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
+          const R kw = dj / (R)a.w[idx[j]];
+          const R tau = (R)md.sip_tau[j];
 #pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int fj = side ? K : 0;
-          const int task = le * NFE + (2 * j + side) * NF + fpj;
-          const int nf = base + fj * str;                    // the face node (a thread of this element)
-          const R sgn = side ? R(1) : R(-1);
-          const R dfi = R(0.5) * dj * sDm[fj * P1 + idx[j]];
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            const int f = (RAIN && v == V::RR) ? 1 : 0;
-            const R alf = sA[f * NT + nf];
+          for (int side = 0; side < 2; ++side) {
+            const int fj = side ? K : 0;
+            const int task = le * NFE + (2 * j + side) * NF + fpj;
+            const int nf = base + fj * str;                  // the face node (a thread of this element)
             const R ju = sJ[v * NFB + task];
-            R term = dfi * ju;
-            if (idx[j] == fj) term += sgn * (sM[v * NFB + task] - tau * ju);
-            Sv[v] += kw * alf * term;
+            R term = R(0.5) * dj * sDm[fj * P1 + idx[j]] * ju;
+            if (idx[j] == fj) term += (side ? R(1) : R(-1)) * (sM[v * NFB + task] - tau * ju);
+            Sv += kw * sA[fa * NT + nf] * term;
           }
         }
+        st(out, N, v, g, Sv);
       }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) st(out, N, v, g, Sv[v]);
     }
     __syncthreads();   // the tiles are reused by the next item
   }
