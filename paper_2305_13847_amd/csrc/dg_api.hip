@@ -71,6 +71,8 @@ struct dg_handle {
   void* stage_w = nullptr;       // adjoint of the step's end state through the sponge
   double* sponge_d = nullptr;    // sponge blending factor per vertical node index
   double* bgf_d = nullptr;       // Gauss basis: background traces on horizontal faces
+  void* tr_u[2] = {nullptr, nullptr};     // Gauss basis: face traces of U' (ping-pong like aux)
+  double* tr_a[2] = {nullptr, nullptr};   // and of T, rho_v
   bool sip = false;              // artificial diffusion on
   double* sip_aK = nullptr;      // per-element viscosity, two fields
   double* sip_av = nullptr;      // vertex means, two fields
@@ -270,6 +272,7 @@ static void free_all(dg_handle* h) {
   for (auto& b : h->stage_x) F(b);
   F(h->stage_w); F(h->sponge_d); F(h->bgf_d);
   F(h->sip_aK); F(h->sip_av); F(h->sip_out);
+  for (int i = 0; i < 2; ++i) { F(h->tr_u[i]); F(h->tr_a[i]); }
   F(h->auxT); F(h->auxS); F(h->auxT2); F(h->auxS2);
   F(h->auxT3); F(h->auxS3); F(h->auxT4); F(h->auxS4);
   F(h->dt_d); F(h->partial); F(h->red_out); F(h->stats);
@@ -470,7 +473,15 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
     ok = ok && A(&h->stage_w, h->state_bytes);
     ok = ok && A((void**)&h->sponge_d, sizeof(double) * hoff);
   }
-  if (p->basis == DG_BASIS_GAUSS) ok = ok && A((void**)&h->bgf_d, sizeof(double) * 5 * 2 * (hoff / p1));
+  if (p->basis == DG_BASIS_GAUSS) {
+    ok = ok && A((void**)&h->bgf_d, sizeof(double) * 5 * 2 * (hoff / p1));
+    // 2D faces of (k+1)^(d-1) quadrature points per element
+    const size_t nfe = (size_t)2 * dim * (dim == 2 ? p1 : p1 * p1);
+    for (int i = 0; i < 2; ++i) {
+      ok = ok && A(&h->tr_u[i], (size_t)nvars * eoff * nfe * rsz);
+      ok = ok && A((void**)&h->tr_a[i], (size_t)2 * eoff * nfe * sizeof(double));
+    }
+  }
   h->sip = p->sip_gamma > 0.0;
   if (h->sip) {
     ok = ok && A((void**)&h->sip_aK, sizeof(double) * 2 * eoff);
@@ -695,17 +706,41 @@ static bool do_split(dg_handle* h, const void* U, const double* guess, double* o
   return Launch<float>::split(h->ka, lc, h->order, h->dim, h->rain, 0, n, U, guess, oT, o1, o2, api, s);
 }
 
+// tin / tout: the Gauss basis' trace buffers of the stage state (read) and of
+// the new state (written in mode 2)
 static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, const double* aS, void* out,
                    const void* U0, double c0, double c1, double c2, hipStream_t s,
-                   double* oT = nullptr, double* oS = nullptr, int flags = 0) {
+                   double* oT = nullptr, double* oS = nullptr, int flags = 0, int tin = 0, int tout = 1) {
   KTimer kt(h, DG_K_STAGE, s);
   if (mode == 2) h->splits += h->nnodes;
   const LaunchCfg lc = launch_cfg(h);
+  KArgs ka = h->ka;
+  if (h->P.basis == DG_BASIS_GAUSS) {
+    ka.tr_u_in = h->tr_u[tin];
+    ka.tr_a_in = h->tr_a[tin];
+    ka.tr_u_out = h->tr_u[tout];
+    ka.tr_a_out = h->tr_a[tout];
+  }
   if (h->prec == DG_FP64)
-    return Launch<double>::rhs(h->ka, h->ka_d, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0,
+    return Launch<double>::rhs(ka, h->ka_d, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0,
                                h->dt_d, c0, c1, c2, oT, oS, flags, s);
-  return Launch<float>::rhs(h->ka, h->ka_d, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d,
+  return Launch<float>::rhs(ka, h->ka_d, lc, h->order, h->dim, h->rain, mode, U, aT, aS, out, U0, h->dt_d,
                             c0, c1, c2, oT, oS, flags, s);
+}
+
+// Gauss basis: face traces of U and its split (aT, aS) into trace buffer tout
+static void do_gauss_trace(dg_handle* h, const void* U, const double* aT, const double* aS, int tout,
+                           hipStream_t s) {
+  if (h->P.basis != DG_BASIS_GAUSS) return;
+  KTimer kt(h, DG_K_OTHER, s);
+  const LaunchCfg lc = launch_cfg(h);
+  KArgs ka = h->ka;
+  ka.tr_u_out = h->tr_u[tout];
+  ka.tr_a_out = h->tr_a[tout];
+  if (h->prec == DG_FP64)
+    Launch<double>::gauss_trace(ka, lc, h->order, h->dim, h->rain, U, aT, aS, s);
+  else
+    Launch<float>::gauss_trace(ka, lc, h->order, h->dim, h->rain, U, aT, aS, s);
 }
 
 // artificial diffusion of the state U into the handle's tendency buffer
@@ -725,7 +760,8 @@ extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t
   if (U == dUdt) return fail(DG_EINVAL, "U and dUdt must not alias");
   if (!do_split(h, U, nullptr, h->auxT, h->auxS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
   if (h->sip) do_sip(h, U, s);
-  do_rhs(h, 0, U, h->auxT, h->auxS, dUdt, nullptr, 0, 0, 0, s, nullptr, nullptr, h->sip ? kSip : 0);
+  do_gauss_trace(h, U, h->auxT, h->auxS, 0, s);
+  do_rhs(h, 0, U, h->auxT, h->auxS, dUdt, nullptr, 0, 0, 0, s, nullptr, nullptr, h->sip ? kSip : 0, 0, 1);
   HIP_TRY(hipGetLastError());
   return DG_OK;
 }
@@ -767,6 +803,7 @@ static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t
   if (first) {
     *cur = 0;
     do_split(h, U, nullptr, aT[0], aS[0], nullptr, 0, s);
+    do_gauss_trace(h, U, aT[0], aS[0], 0, s);
   }
   const int ns = h->rk == DG_SSPRK43 ? 4 : 3;
   const void* in43[4] = {U, B1, B2, B1};
@@ -785,7 +822,7 @@ static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t
     const int flags = (last && (step & 3) == 3 ? kRefreshRvs : 0) | (last && h->sponge ? kSponge : 0) |
                       (h->sip ? kSip : 0);
     if (h->sip) do_sip(h, in, s);
-    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], flags);
+    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], flags, a, b);
     *cur = b;
   }
   HIP_TRY(hipGetLastError());

@@ -62,6 +62,13 @@ struct KArgs {
   // concatenated columns (hoff / (k+1) + ez) and side s (0 bottom, 1 top)
   const double* bgf;
   int bgf_n;
+  // basis 1: face traces of the stage state (read) and of the new state
+  // (written by MODE 2): U' at tr_u[(v * etot + e) * NFE + f], T and rho_v at
+  // tr_a[(c * etot + e) * NFE + f] for face point f of element e
+  const void* tr_u_in;
+  const double* tr_a_in;
+  void* tr_u_out;
+  double* tr_a_out;
   // artificial diffusion (Lobatto basis): collocation derivative matrix
   // Dm[a*(k+1)+i] = l_i'(x_a), Lobatto nodes, per-element viscosity aK[2][e],
   // vertex means av[2][vertex] and the diffusive tendency (state layout)

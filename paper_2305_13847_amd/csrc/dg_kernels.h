@@ -412,7 +412,11 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
                                                const R* Uq, const R* U0q, const R* Rv, double T, double rvs,
                                                R* __restrict__ out, double dtm, double c0, double c1,
                                                double c2, double* __restrict__ oT,
-                                               double* __restrict__ oS, int flags, int& iters, int& bad) {
+                                               double* __restrict__ oS, int flags, int& iters, int& bad,
+                                               R* Unew = nullptr, double* Tnew = nullptr,
+                                               double* Snew = nullptr) {
+  // (Unew, Tnew, Snew), when given, receive the stored new state and its
+  // stored (T, rho_vs)
   using V = Vars<D, RAIN>;
   constexpr int NV = V::NV;
   if (MODE == 0) {
@@ -434,6 +438,10 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
   if (flags & kSponge) sponge_point<R, D, RAIN>(a, iz, Un);
 #pragma unroll
   for (int v = 0; v < NV; ++v) st(out, N, v, g, Un[v]);
+  if (Unew) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Unew[v] = Un[v];
+  }
   if (MODE == 2) {
     // split of the new state (FP64), warm-started at this node's (T, rho_vs);
     // bg = (rho_d, rho_m, rho_r, E) of the background at this node
@@ -456,8 +464,11 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
     const SplitOut s = split_point_anchor(a, rd, rm, rr, re, T, A, rvs < rm);
     iters = s.iters;
     bad = s.bad;
+    const double rvs_st = ((flags & kRefreshRvs) && s.bad == 0) ? rho_vs(a, s.T) : s.rvs;
     st(oT, N, 0, g, s.T);
-    st(oS, N, 0, g, ((flags & kRefreshRvs) && s.bad == 0) ? rho_vs(a, s.T) : s.rvs);
+    st(oS, N, 0, g, rvs_st);
+    if (Tnew) *Tnew = s.T;
+    if (Snew) *Snew = rvs_st;
   }
 }
 

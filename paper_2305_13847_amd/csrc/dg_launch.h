@@ -91,6 +91,16 @@ struct Launch {
     });
   }
 
+  // Gauss basis: face traces of a state and its split
+  static bool gauss_trace(const KArgs& a, LaunchCfg lc, int K, int D, int rain, const void* U,
+                          const double* auxT, const double* auxS, hipStream_t s) {
+    return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
+      constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
+      hipLaunchKernelGGL((gauss_trace_kernel<R, K_, D_, R_>), dim3(lc.grid), dim3(lc.threads), 0, s, a,
+                         (const R*)U, auxT, auxS);
+    });
+  }
+
   // artificial diffusion: alpha_K, vertex means (per member), tendency
   static bool sip(const KArgs& a, LaunchCfg lc, int K, int D, int rain, int nmembers, const long long* nvert,
                   const void* U, hipStream_t s) {
