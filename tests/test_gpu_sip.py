@@ -138,3 +138,25 @@ def test_refused_combinations():
     with pytest.raises(lib.DGError) as ei:
         lib.for_case(g, precision=lib.DG_FP64, sip_gamma=GAM)
     assert ei.value.status == lib.DG_EUNSUPPORTED
+
+
+def test_batch_members_match_single_runs():
+    # two members of different size: per-member vertex tables and offsets
+    cases = [_windy(synth.moist_bubble(n=(10, 5), order=3, seed=21)),
+             _windy(synth.moist_bubble(n=(14, 7), order=3, seed=22, amp=1.0), u=6.0)]
+    lib = _lib()
+    dg = lib.for_ensemble(cases, precision=lib.DG_FP64, sip_gamma=GAM)
+    U = torch.cat([torch.tensor(c.U).reshape(c.nvars, -1) for c in cases], dim=1).contiguous().cuda()
+    U = U.reshape(dg.shape)
+    dts = np.array([c.dt for c in cases])
+    dg.rk_step(U, dts, 4)
+    Uh = U.cpu().numpy().reshape(5, -1)
+    off = 0
+    for c in cases:
+        n = c.mesh.ne * c.mesh.npe
+        got = Uh[:, off:off + n].reshape(c.U.shape)
+        off += n
+        ref, _ = O.Oracle.for_case(c, sip_gamma=GAM).rk(c.U, c.dt, 4)
+        floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
+        err = rel_l2(c.mesh, got, ref, floor=floor)
+        assert np.all(err < 1e-11), err
