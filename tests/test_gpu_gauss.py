@@ -45,6 +45,8 @@ CASES = {
     "bubble2d_q4": lambda: synth.moist_bubble(n=(12, 6), order=4, seed=12, basis=G),
     "rain3d_q2": lambda: synth.warm_rain_3d(n=(5, 4, 3), order=2, seed=15, basis=G),
     "rain3d_q3": lambda: synth.warm_rain_3d(n=(4, 4, 3), order=3, seed=14, basis=G),
+    "rain3d_q1": lambda: synth.warm_rain_3d(n=(6, 5, 4), order=1, seed=17, basis=G),
+    "rain3d_q4": lambda: synth.warm_rain_3d(n=(3, 3, 3), order=4, seed=18, basis=G),
 }
 
 

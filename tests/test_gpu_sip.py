@@ -53,6 +53,8 @@ CASES = {
     "bubble2d_q4": lambda: _windy(synth.moist_bubble(n=(12, 6), order=4, seed=12)),
     "rain3d_q2": lambda: _windy(synth.warm_rain_3d(n=(5, 4, 3), order=2, seed=15)),
     "rain3d_q3": lambda: _windy(synth.warm_rain_3d(n=(4, 4, 3), order=3, seed=14)),
+    "rain3d_q1": lambda: _windy(synth.warm_rain_3d(n=(6, 5, 4), order=1, seed=17)),
+    "rain3d_q4": lambda: _windy(synth.warm_rain_3d(n=(3, 3, 3), order=4, seed=18)),
 }
 
 
@@ -160,3 +162,17 @@ def test_batch_members_match_single_runs():
         floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
         err = rel_l2(c.mesh, got, ref, floor=floor)
         assert np.all(err < 1e-11), err
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_with_sponge_and_both_schemes(scheme):
+    # the last stage of every step carries both flags (diffusion, sponge)
+    c = CASES["rain3d_q2"]()
+    lib = _lib()
+    over = dict(sip_gamma=GAM, sponge_zD=5.0e3, sponge_alpha=0.5)
+    dg, U = _gpu(c, lib.DG_FP64, rk=lib.DG_SSPRK43 if scheme == 0 else lib.DG_SSPRK33, **over)
+    dg.rk_step(U, c.dt, 5)
+    ref, _ = O.Oracle.for_case(c, **over).rk(c.U, c.dt, 5, scheme=scheme)
+    floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
+    err = rel_l2(c.mesh, U.cpu().numpy().reshape(c.U.shape), ref, floor=floor)
+    assert np.all(err < 1e-11), err
