@@ -265,38 +265,63 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
       }
     }
     __syncthreads();
-    // D. the tendency at every node, one variable at a time
+    // D. the tendency at every node.  The line coefficients d_j Dhat[i_j][a]
+    // alpha_a and the face coefficients depend on the viscosity field, not on
+    // the variable: they are formed once, then each variable reads only its
+    // gradients and face values.
     if (active) {
+      constexpr int NA = RAIN ? 2 : 1;       // viscosity fields in use
+      R cw[NA][D][P1];                       // volume: d_j Dhat[i_j][a] alpha(line node a)
+      R cl[NA][D][2];                        // faces: d_j / w_{i_j} alpha_f, per side
+      R cd[D][2];                            // d_j / 2 D[f_j][i_j]
+      R ct[D];                               // tau_j
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+        const int base = t - idx[j] * str;
+        const R dj = (R)md.two_over_h[j];
+        const R kw = dj / (R)a.w[idx[j]];
+        ct[j] = (R)md.sip_tau[j];
+#pragma unroll
+        for (int b = 0; b < P1; ++b) {
+          const R db = dj * sDh[idx[j] * P1 + b];
+#pragma unroll
+          for (int f = 0; f < NA; ++f) cw[f][j][b] = db * sA[f * NT + base + b * str];
+        }
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int fj = side ? K : 0;
+          cd[j][side] = R(0.5) * dj * sDm[fj * P1 + idx[j]];
+#pragma unroll
+          for (int f = 0; f < NA; ++f) cl[f][j][side] = kw * sA[f * NT + base + fj * str];
+        }
+      }
 #pragma unroll 1
       for (int v = 0; v < NV; ++v) {
-        const int fa = (RAIN && v == V::RR) ? 1 : 0;
+        const bool rr = RAIN && v == V::RR;
         R Sv = R(0);
 #pragma unroll
         for (int j = 0; j < D; ++j) {
           const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
           const int base = t - idx[j] * str;
-          const R dj = (R)md.two_over_h[j];
           // volume
           R acc = R(0);
 #pragma unroll
           for (int b = 0; b < P1; ++b)
-            acc += sDh[idx[j] * P1 + b] * (sA[fa * NT + base + b * str] * sG[(j * NV + v) * NT + base + b * str]);
-          Sv -= dj * acc;
+            acc += (rr ? cw[NA - 1][j][b] : cw[0][j][b]) * sG[(j * NV + v) * NT + base + b * str];
+          Sv -= acc;
           // faces: this node's line meets the minus face (side 0) and the plus face (side 1)
           int fpj;
           if (D == 2) fpj = (j == 0) ? idx[1] : idx[0];
           else fpj = (j == 0) ? idx[1] + P1 * idx[2] : (j == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
-          const R kw = dj / (R)a.w[idx[j]];
-          const R tau = (R)md.sip_tau[j];
 #pragma unroll
           for (int side = 0; side < 2; ++side) {
             const int fj = side ? K : 0;
             const int task = le * NFE + (2 * j + side) * NF + fpj;
-            const int nf = base + fj * str;                  // the face node (a thread of this element)
             const R ju = sJ[v * NFB + task];
-            R term = R(0.5) * dj * sDm[fj * P1 + idx[j]] * ju;
-            if (idx[j] == fj) term += (side ? R(1) : R(-1)) * (sM[v * NFB + task] - tau * ju);
-            Sv += kw * sA[fa * NT + nf] * term;
+            R term = cd[j][side] * ju;
+            if (idx[j] == fj) term += (side ? R(1) : R(-1)) * (sM[v * NFB + task] - ct[j] * ju);
+            Sv += (rr ? cl[NA - 1][j][side] : cl[0][j][side]) * term;
           }
         }
         st(out, N, v, g, Sv);
