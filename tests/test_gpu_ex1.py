@@ -14,6 +14,9 @@
 - Self-convergence on nested meshes (30r x r elements) against a finer Q4
   run: the space-time l2(L2) error of Q3 falls at rate > 2.5 for every
   variable (the Lobatto collocation converges at about k for rho' and E').
+- In the paper's Legendre/Gauss basis the same Q3 study converges at rate
+  > 3.8 for every variable (order k+1), with rho' errors at least five times
+  below the Lobatto ones (measured: 4.6 against 3.0, 22 times).
 """
 import numpy as np
 import pytest
@@ -70,3 +73,15 @@ def test_self_convergence_small():
     e1, e2 = np.array(rows[0]["err"]), np.array(rows[1]["err"])
     rate = np.log(e1 / e2) / np.log(2.0)
     assert np.all(rate > 2.5), rate
+
+
+def test_gauss_basis_recovers_order_k_plus_1():
+    from paper_2305_13847_amd import ex1_convergence as ex
+    out = {}
+    for basis in ("lobatto", "gauss"):
+        rows = ex.study([4, 8], [3], 16, 4, 300.0, 3, log=lambda m: print(m, flush=True), basis=basis)
+        e1, e2 = np.array(rows[0]["err"]), np.array(rows[1]["err"])
+        out[basis] = (e2, np.log(e1 / e2) / np.log(2.0))
+        print(basis, "errors", e2, "rates", out[basis][1], flush=True)
+    assert np.all(out["gauss"][1] > 3.8), out["gauss"][1]
+    assert out["gauss"][0][0] < out["lobatto"][0][0] / 5.0
