@@ -175,3 +175,22 @@ def test_batch_members_match_single_runs():
         floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
         err = rel_l2(c.mesh, got, ref, floor=floor)
         assert np.all(err < 1e-11), err
+
+
+def test_mixed_calls_on_one_handle():
+    # steps with an odd count, then dg_rhs, then more steps: every call starts
+    # from traces of its own input state, whatever buffer the last stage left
+    c = CASES["bubble2d_q3"]()
+    lib = _lib()
+    dg, U = _gpu(c, lib.DG_FP64)
+    o = O.Oracle.for_case(c)
+    dg.rk_step(U, c.dt, 3)
+    ref3, _ = o.rk(c.U, c.dt, 3)
+    R = dg.rhs(U).cpu().numpy().reshape(c.U.shape)
+    err = rel_max(R, o.rhs(ref3))
+    assert np.all(err < 1e-10), err
+    dg.rk_step(U, c.dt, 2)
+    ref5, _ = o.rk(ref3, c.dt, 2)
+    floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref5[-1] ** 2))
+    err = rel_l2(c.mesh, U.cpu().numpy().reshape(c.U.shape), ref5, floor=floor)
+    assert np.all(err < 1e-11), err
