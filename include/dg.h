@@ -139,7 +139,9 @@ typedef struct {
 /* Fill *p with the paper's constants, no rain, FP64, SSPRK(4,3), no sponge. */
 void dg_default_params(dg_params* p);
 
-/* Create a handle for one mesh.  order k in 1..4, nvars = 3 + dim (rain = 0)
+/* Create a handle for one mesh.  order k in 1..7 in 2D and 1..4 in 3D (a 3D
+ * element of order 5 or more has more nodes than a thread block; one thread
+ * owns one node), nvars = 3 + dim (rain = 0)
  * or 4 + dim (rain = 1), otherwise DG_EINVAL.  A handle holds fewer than
  * 2^29 nodes in FP64 and 2^30 in FP32 bulk (each variable's array stays below
  * 4 GiB), otherwise DG_EINVAL.  *out receives the handle. */

@@ -175,12 +175,42 @@ static double legendre_P(int k, double x) {
   return p1;
 }
 
+// P_n and P_n' at x (three-term recurrence; P_n' from (1 - x^2) P_n' = n (P_{n-1} - x P_n))
+static void legendre_pd(int n, double x, double* P, double* dP) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) { *P = 1.0; *dP = 0.0; return; }
+  for (int m = 1; m < n; ++m) {
+    const double p2 = ((2 * m + 1) * x * p1 - m * p0) / (m + 1);
+    p0 = p1;
+    p1 = p2;
+  }
+  *P = p1;
+  *dP = n * (p0 - x * p1) / (1.0 - x * x);
+}
+
+// Lobatto nodes: closed forms for k <= 4; above, the roots of P_k' by Newton
+// (with P_k'' from Legendre's equation) from the Chebyshev-Lobatto points
 static void lobatto_nodes(int k, double* x) {
   switch (k) {
-    case 1: x[0] = -1; x[1] = 1; break;
-    case 2: x[0] = -1; x[1] = 0; x[2] = 1; break;
-    case 3: x[0] = -1; x[1] = -1 / std::sqrt(5.0); x[2] = -x[1]; x[3] = 1; break;
-    default: x[0] = -1; x[1] = -std::sqrt(3.0 / 7.0); x[2] = 0; x[3] = -x[1]; x[4] = 1; break;
+    case 1: x[0] = -1; x[1] = 1; return;
+    case 2: x[0] = -1; x[1] = 0; x[2] = 1; return;
+    case 3: x[0] = -1; x[1] = -1 / std::sqrt(5.0); x[2] = -x[1]; x[3] = 1; return;
+    case 4: x[0] = -1; x[1] = -std::sqrt(3.0 / 7.0); x[2] = 0; x[3] = -x[1]; x[4] = 1; return;
+    default: break;
+  }
+  x[0] = -1.0;
+  x[k] = 1.0;
+  for (int i = 1; i < k; ++i) {
+    double t = -std::cos(M_PI * i / k);
+    for (int it = 0; it < 60; ++it) {
+      double P, dP;
+      legendre_pd(k, t, &P, &dP);
+      const double d2P = (2.0 * t * dP - k * (k + 1.0) * P) / (1.0 - t * t);
+      const double step = dP / d2P;
+      t -= step;
+      if (std::fabs(step) < 1e-16) break;
+    }
+    x[i] = t;
   }
 }
 
@@ -214,7 +244,23 @@ static void lobatto_tables(int k, double* w, double* Dhat, double* Dout = nullpt
 // the Lagrange basis at the element ends, l_i(-1) and l_i(+1).
 static void gauss_tables(int k, double* x, double* w, double* Dhat, double* lm, double* lp) {
   const int p1 = k + 1;
-  switch (k) {
+  if (k > 4) {
+    // the roots of P_{k+1} by Newton from the cosine guesses; w = 2 / ((1 - x^2) P'^2)
+    for (int i = 0; i < p1; ++i) {
+      double t = -std::cos(M_PI * (i + 0.75) / (p1 + 0.5));
+      for (int it = 0; it < 60; ++it) {
+        double P, dP;
+        legendre_pd(p1, t, &P, &dP);
+        const double step = P / dP;
+        t -= step;
+        if (std::fabs(step) < 1e-16) break;
+      }
+      double P, dP;
+      legendre_pd(p1, t, &P, &dP);
+      x[i] = t;
+      w[i] = 2.0 / ((1.0 - t * t) * dP * dP);
+    }
+  } else switch (k) {
     case 1: x[1] = 1.0 / std::sqrt(3.0); w[0] = w[1] = 1.0; break;
     case 2: x[2] = std::sqrt(0.6); x[1] = 0.0; w[1] = 8.0 / 9.0; w[0] = w[2] = 5.0 / 9.0; break;
     case 3: {
@@ -233,7 +279,8 @@ static void gauss_tables(int k, double* x, double* w, double* Dhat, double* lm, 
       break;
     }
   }
-  for (int i = 0; i < p1 / 2; ++i) x[i] = -x[k - i];
+  if (k <= 4)
+    for (int i = 0; i < p1 / 2; ++i) x[i] = -x[k - i];
   double lam[kMaxP1];
   for (int i = 0; i < p1; ++i) {
     lam[i] = 1.0;
@@ -349,7 +396,8 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
   if (nmembers < 1) return fail(DG_EINVAL, "nmembers must be >= 1");
   const int dim = meshes[0].dim;
   if (dim != 2 && dim != 3) return fail(DG_EINVAL, "dim must be 2 or 3 (got %d)", dim);
-  if (order < 1 || order > kMaxOrder) return fail(DG_EINVAL, "order must be in 1..%d (got %d)", kMaxOrder, order);
+  if (order < 1 || order > (dim == 2 ? kMaxOrder : 4))
+    return fail(DG_EINVAL, "order must be in 1..%d for dim %d (got %d)", dim == 2 ? kMaxOrder : 4, dim, order);
   if (p->rain != 0 && p->rain != 1) return fail(DG_EINVAL, "rain must be 0 or 1");
   if (nvars != (p->rain ? 4 : 3) + dim)
     return fail(DG_EINVAL, "nvars must be %d for dim=%d rain=%d (got %d)", (p->rain ? 4 : 3) + dim, dim, p->rain, nvars);

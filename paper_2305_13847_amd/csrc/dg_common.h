@@ -6,7 +6,7 @@
 
 namespace dgm {
 
-constexpr int kMaxOrder = 4;
+constexpr int kMaxOrder = 7;     // 2D; 3D kernels are instantiated up to 4
 constexpr int kMaxP1 = kMaxOrder + 1;
 
 // One ensemble member: a structured box.  Elements of all members are

@@ -21,6 +21,9 @@ bool dispatch_shape(int K, int D, int rain, F&& f) {
   DGM_CASE(2, 2, 0) DGM_CASE(2, 2, 1) DGM_CASE(2, 3, 0) DGM_CASE(2, 3, 1)
   DGM_CASE(3, 2, 0) DGM_CASE(3, 2, 1) DGM_CASE(3, 3, 0) DGM_CASE(3, 3, 1)
   DGM_CASE(4, 2, 0) DGM_CASE(4, 2, 1) DGM_CASE(4, 3, 0) DGM_CASE(4, 3, 1)
+  // 2D only above 4: a 3D element of order >= 5 has more nodes than a block
+  DGM_CASE(5, 2, 0) DGM_CASE(5, 2, 1) DGM_CASE(6, 2, 0) DGM_CASE(6, 2, 1)
+  DGM_CASE(7, 2, 0) DGM_CASE(7, 2, 1)
 #undef DGM_CASE
   return false;
 }

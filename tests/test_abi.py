@@ -105,3 +105,13 @@ def test_create_without_a_device_fails_loudly():
     with pytest.raises(lib.DGError) as e:
         lib.for_case(c, precision=lib.DG_FP64)
     assert "dg status" in str(e.value)
+
+
+@pytest.mark.parametrize("dim,order", [(3, 5), (2, 8), (2, 0)])
+def test_order_range_is_checked_before_the_device(dim, order):
+    # orders 1..7 in 2D and 1..4 in 3D; the check runs before any device call
+    from paper_2305_13847_amd import synth
+    c = synth.periodic_smooth(n=(2,) * dim, order=max(order, 1), dim=dim, seed=1)
+    with pytest.raises(lib.DGError) as e:
+        lib.DG(c.mesh, order, c.nvars, lib.params_for_case(c, lib.DG_FP64))
+    assert e.value.status == lib.DG_EINVAL, str(e.value)
