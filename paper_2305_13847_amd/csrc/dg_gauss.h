@@ -254,8 +254,14 @@ gauss_trace_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ 
   }
 }
 
+// FP32 up to Q3 in 3D and Q5 in 2D: 4 wavefronts per SIMD (128 VGPRs; with
+// the face fluxes in the flux tile, four blocks fit a CU's LDS). Higher
+// orders and FP64 would spill there and are left to the compiler.
+template <typename R, int K, int D>
+constexpr int gauss_min_waves() { return (sizeof(R) == 4 && K <= (D == 3 ? 3 : 5)) ? 4 : 1; }
+
 template <typename R, int K, int D, int RAIN, int MODE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gauss_min_waves<R, K, D>())))
 rhs_gauss_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
                  const double* __restrict__ auxS, R* __restrict__ out, const R* __restrict__ U0,
                  const double* __restrict__ dt_m, double c0, double c1, double c2,
@@ -268,7 +274,7 @@ rhs_gauss_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ au
   __shared__ R sF[D * NV * NT];
   __shared__ R sU[NV * NT];
   __shared__ double sT[NT], sRv[NT];
-  __shared__ R sFs[NV * NFB];
+  R* const sFs = sF;   // the face fluxes reuse the flux tile once the volume term has read it
   __shared__ R sD[P1 * P1];
   __shared__ double sL[2][kMaxP1];
   const int t = threadIdx.x;
@@ -278,115 +284,114 @@ rhs_gauss_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ au
     sL[1][t] = a.gl_p[t];
   }
   const int epb = (int)blockDim.x / NP;
-  const ItemWalk walk(a.nitems);
-#pragma clang loop unroll(disable)
-  for (int kk = 0;; ++kk) {
-    const int it_ = walk.item(kk);
-    if (it_ < 0) break;
-    const Item item = a.items[it_];
-    const MemberDesc& md = a.mem[item.member];
-    const int le = t / NP, n = t - le * NP;
-    const int e = item.e0 + le;
-    const bool active = e < md.ne;
-    const unsigned N = a.nnodes;
-    const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
-    const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
-    int idx[3];
-    idx[0] = n % P1;
-    idx[1] = (n / P1) % P1;
-    idx[2] = (D == 3) ? n / (P1 * P1) : 0;
-    const int iz = md.hoff + ec.c[D - 1] * P1 + idx[D - 1];
-    // 1. node pass
-    R Uq[NV];
-    double T = 300.0, rvs = 0.0;
-    if (active) {
+  // one work item per block: a loop over items lets the compiler keep
+  // loop-invariant values live across the whole body, which about doubles the
+  // registers (and halves the occupancy)
+  const int it_ = ItemWalk(a.nitems).item(0);
+  if (it_ < 0) return;
+  const Item item = a.items[it_];
+  const MemberDesc& md = a.mem[item.member];
+  const int le = t / NP, n = t - le * NP;
+  const int e = item.e0 + le;
+  const bool active = e < md.ne;
+  const unsigned N = a.nnodes;
+  const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
+  const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
+  int idx[3];
+  idx[0] = n % P1;
+  idx[1] = (n / P1) % P1;
+  idx[2] = (D == 3) ? n / (P1 * P1) : 0;
+  const int iz = md.hoff + ec.c[D - 1] * P1 + idx[D - 1];
+  // 1. node pass
+  R Uq[NV];
+  double T = 300.0, rvs = 0.0;
+  if (active) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Uq[v] = ld(U, N, v, g);
-      T = ld(auxT, N, 0, g);
-      rvs = ld(auxS, N, 0, g);
+    for (int v = 0; v < NV; ++v) Uq[v] = ld(U, N, v, g);
+    T = ld(auxT, N, 0, g);
+    rvs = ld(auxS, N, 0, g);
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Uq[v] = R(0);
+  }
+  Pt<R, D, RAIN> q;
+  eval_point<R, D, RAIN>(a, Uq, T, rvs, active ? iz : md.hoff, q);
+  stage_flux<R, K, D, RAIN, 0>(q, sF);
+  stage_flux<R, K, D, RAIN, 1>(q, sF + NV * NT);
+  if constexpr (D == 3) stage_flux<R, K, D, RAIN, 2>(q, sF + 2 * NV * NT);
+  stage_node_tiles<R, K, D, RAIN>(a, active, iz, g, Uq, T, rvs, sU, sT, sRv);
+  __syncthreads();
+  R Rv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Rv[v] = R(0);
+  if (active) {
+    volume_dir<R, K, D, RAIN, 0>(md, idx[0], sF, Rv, sD, t);
+    volume_dir<R, K, D, RAIN, 1>(md, idx[1], sF + NV * NT, Rv, sD, t);
+    if constexpr (D == 3) volume_dir<R, K, D, RAIN, 2>(md, idx[2], sF + 2 * NV * NT, Rv, sD, t);
+    sources<R, D, RAIN>(a, Uq, q, Rv);
+  }
+  __syncthreads();   // the volume term's reads of sF are over
+  // 2. face pass
+  for (int task = t; task < epb * NFE; task += (int)blockDim.x) {
+    const int fle = task / NFE;
+    const int r = task - fle * NFE;
+    const int f = r / NF;
+    const int fp = r - f * NF;
+    const int J = f >> 1, side = f & 1;
+    R Fs[NV];
+    if (item.e0 + fle < md.ne) {
+      if (J == 0) gauss_face<R, K, D, RAIN, 0>(a, md, item, fle, side, fp, sU, sT, sRv, sL, Fs);
+      else if (J == 1 || D == 2) gauss_face<R, K, D, RAIN, 1>(a, md, item, fle, side, fp, sU, sT, sRv, sL, Fs);
+      else if constexpr (D == 3) gauss_face<R, K, D, RAIN, 2>(a, md, item, fle, side, fp, sU, sT, sRv, sL, Fs);
     } else {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) Uq[v] = R(0);
+      for (int v = 0; v < NV; ++v) Fs[v] = R(0);
     }
-    Pt<R, D, RAIN> q;
-    eval_point<R, D, RAIN>(a, Uq, T, rvs, active ? iz : md.hoff, q);
-    stage_flux<R, K, D, RAIN, 0>(q, sF);
-    stage_flux<R, K, D, RAIN, 1>(q, sF + NV * NT);
-    if constexpr (D == 3) stage_flux<R, K, D, RAIN, 2>(q, sF + 2 * NV * NT);
-    stage_node_tiles<R, K, D, RAIN>(a, active, iz, g, Uq, T, rvs, sU, sT, sRv);
-    __syncthreads();
-    R Rv[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Rv[v] = R(0);
-    if (active) {
-      volume_dir<R, K, D, RAIN, 0>(md, idx[0], sF, Rv, sD, t);
-      volume_dir<R, K, D, RAIN, 1>(md, idx[1], sF + NV * NT, Rv, sD, t);
-      if constexpr (D == 3) volume_dir<R, K, D, RAIN, 2>(md, idx[2], sF + 2 * NV * NT, Rv, sD, t);
-      sources<R, D, RAIN>(a, Uq, q, Rv);
+    for (int v = 0; v < NV; ++v) sFs[v * NFB + task] = Fs[v];
+  }
+  __syncthreads();
+  // 3. lifting: + l_i(-1)/w_i F*(minus face) - l_i(+1)/w_i F*(plus face),
+  // then the stage update and the split
+  int iters = 0, bad = 0;
+  if (active) {
+#pragma unroll
+    for (int J = 0; J < D; ++J) {
+      const int i = idx[J];
+      int fpJ;
+      if (D == 2) fpJ = (J == 0) ? idx[1] : idx[0];
+      else fpJ = (J == 0) ? idx[1] + P1 * idx[2] : (J == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
+      const int base = le * NFE + 2 * J * NF + fpJ;
+      const R km = (R)(md.two_over_h[J] * a.lift_m[i]);
+      const R kp = (R)(md.two_over_h[J] * a.lift_p[i]);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) Rv[v] += km * sFs[v * NFB + base] - kp * sFs[v * NFB + base + NF];
     }
-    // 2. face pass
-    for (int task = t; task < epb * NFE; task += (int)blockDim.x) {
-      const int fle = task / NFE;
-      const int r = task - fle * NFE;
-      const int f = r / NF;
-      const int fp = r - f * NF;
-      const int J = f >> 1, side = f & 1;
-      R Fs[NV];
-      if (item.e0 + fle < md.ne) {
-        if (J == 0) gauss_face<R, K, D, RAIN, 0>(a, md, item, fle, side, fp, sU, sT, sRv, sL, Fs);
-        else if (J == 1 || D == 2) gauss_face<R, K, D, RAIN, 1>(a, md, item, fle, side, fp, sU, sT, sRv, sL, Fs);
-        else if constexpr (D == 3) gauss_face<R, K, D, RAIN, 2>(a, md, item, fle, side, fp, sU, sT, sRv, sL, Fs);
-      } else {
+    R U0q[NV];
+    const double dtm = (MODE != 0) ? dt_m[item.member] : 0.0;
+    if (MODE != 0 && c0 != 0.0) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) Fs[v] = R(0);
-      }
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sFs[v * NFB + task] = Fs[v];
+      for (int v = 0; v < NV; ++v) U0q[v] = ld(U0, N, v, g);
     }
-    __syncthreads();
-    // 3. lifting: + l_i(-1)/w_i F*(minus face) - l_i(+1)/w_i F*(plus face),
-    // then the stage update and the split
-    int iters = 0, bad = 0;
-    if (active) {
-#pragma unroll
-      for (int J = 0; J < D; ++J) {
-        const int i = idx[J];
-        int fpJ;
-        if (D == 2) fpJ = (J == 0) ? idx[1] : idx[0];
-        else fpJ = (J == 0) ? idx[1] + P1 * idx[2] : (J == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
-        const int base = le * NFE + 2 * J * NF + fpJ;
-        const R km = (R)(md.two_over_h[J] * a.lift_m[i]);
-        const R kp = (R)(md.two_over_h[J] * a.lift_p[i]);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) Rv[v] += km * sFs[v * NFB + base] - kp * sFs[v * NFB + base + NF];
-      }
-      R U0q[NV];
-      const double dtm = (MODE != 0) ? dt_m[item.member] : 0.0;
-      if (MODE != 0 && c0 != 0.0) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) U0q[v] = ld(U0, N, v, g);
-      }
-      double bg[4] = {a.bg_rd[iz], a.bg_rm[iz], RAIN ? a.bg_rr[iz] : 0.0, a.bg_E[iz]};
-      if (MODE == 2) {
-        // the new state and its split go back to the tiles: every face-pass
-        // read of them ended at the barrier above
-        R Unew[NV];
-        double Tnew = 300.0, Snew = 0.0;
-        stage_epilogue<R, D, RAIN, MODE>(a, bg, iz, g, N, Uq, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS,
-                                         flags, iters, bad, Unew, &Tnew, &Snew);
-        stage_node_tiles<R, K, D, RAIN>(a, true, iz, g, Unew, Tnew, Snew, sU, sT, sRv);
-      } else {
-        stage_epilogue<R, D, RAIN, MODE>(a, bg, iz, g, N, Uq, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS,
-                                         flags, iters, bad);
-      }
-    }
+    double bg[4] = {a.bg_rd[iz], a.bg_rm[iz], RAIN ? a.bg_rr[iz] : 0.0, a.bg_E[iz]};
     if (MODE == 2) {
-      record_stats(a, iters, bad);
-      __syncthreads();
-      // 4. the traces of the new state for the next stage
-      write_traces<R, K, D, RAIN>(a, md, item, epb, sU, sT, sRv, sL);
+      // the new state and its split go back to the tiles: every face-pass
+      // read of them ended at the barrier above
+      R Unew[NV];
+      double Tnew = 300.0, Snew = 0.0;
+      stage_epilogue<R, D, RAIN, MODE>(a, bg, iz, g, N, Uq, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS,
+                                       flags, iters, bad, Unew, &Tnew, &Snew);
+      stage_node_tiles<R, K, D, RAIN>(a, true, iz, g, Unew, Tnew, Snew, sU, sT, sRv);
+    } else {
+      stage_epilogue<R, D, RAIN, MODE>(a, bg, iz, g, N, Uq, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS,
+                                       flags, iters, bad);
     }
-    __syncthreads();   // the tiles are reused by the next item
+  }
+  if (MODE == 2) {
+    record_stats(a, iters, bad);
+    __syncthreads();
+    // 4. the traces of the new state for the next stage
+    write_traces<R, K, D, RAIN>(a, md, item, epb, sU, sT, sRv, sL);
   }
 }
 

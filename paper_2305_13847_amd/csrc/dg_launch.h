@@ -80,7 +80,9 @@ struct Launch {
       // the persistent (looping) variant only when the grid is smaller than the items
       const bool persist = (int)grid.x < grid_for_items(a.nitems);
       if (a.basis == 1) {
-        // Gauss nodes: one kernel walks the items for any grid
+        // Gauss nodes: one block per work item whatever the persistence
+        // setting (the kernel has no item loop)
+        grid = dim3(grid_for_items(a.nitems));
         if (mode == 0) DGM_RHS(rhs_gauss_kernel, 0);
         else if (mode == 1) DGM_RHS(rhs_gauss_kernel, 1);
         else DGM_RHS(rhs_gauss_kernel, 2);
