@@ -111,12 +111,15 @@ struct Launch {
                   const void* U, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      hipLaunchKernelGGL((sip_alpha_kernel<R, K_, D_, R_>), dim3(lc.grid), dim3(lc.threads), 0, s, a,
+      // one block per work item whatever the persistence setting (the SIP
+      // kernels have no item loop)
+      const dim3 grid(grid_for_items(a.nitems));
+      hipLaunchKernelGGL((sip_alpha_kernel<R, K_, D_, R_>), grid, dim3(lc.threads), 0, s, a,
                          (const R*)U);
       for (int m = 0; m < nmembers; ++m)
         hipLaunchKernelGGL((sip_vertex_kernel<D_>), dim3((unsigned)((nvert[m] + 127) / 128)), dim3(128), 0, s,
                            a, m);
-      hipLaunchKernelGGL((sip_kernel<R, K_, D_, R_>), dim3(lc.grid), dim3(lc.threads), 0, s, a, (const R*)U);
+      hipLaunchKernelGGL((sip_kernel<R, K_, D_, R_>), grid, dim3(lc.threads), 0, s, a, (const R*)U);
     });
   }
 

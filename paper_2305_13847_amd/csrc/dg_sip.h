@@ -31,55 +31,53 @@ sip_alpha_kernel(KArgs a, const R* __restrict__ U) {
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NT = S::NT;
   __shared__ double sm[2][NT];
-  const ItemWalk walk(a.nitems);
-  for (int kk = 0;; ++kk) {
-    const int it_ = walk.item(kk);
-    if (it_ < 0) break;
-    const int t = threadIdx.x;
-    const Item item = a.items[it_];
-    const MemberDesc& md = a.mem[item.member];
-    const int le = t / NP, n = t - le * NP;
-    const int e = item.e0 + le;
-    double s0 = 0.0, s1 = 0.0;
-    if (e < md.ne) {
-      const unsigned N = a.nnodes;
-      const unsigned g = (unsigned)(md.eoff + e) * NP + n;
-      const ElemCoord<D> ec = item_coord<D>(md, item, le);
-      const int idx[3] = {n % P1, (n / P1) % P1, D == 3 ? n / (P1 * P1) : 0};
-      const int iz = md.hoff + ec.c[D - 1] * P1 + idx[D - 1];
-      const double rd = a.bg_rd[iz] + (double)ld(U, N, V::RD, g);
-      const double rm = a.bg_rm[iz] + (double)ld(U, N, V::RM, g);
-      const double rr = RAIN ? a.bg_rr[iz] + (double)ld(U, N, V::RR, g) : 0.0;
-      const double irho = 1.0 / (rd + rm + rr);
-      double w = md.J;
+  // one work item per block (no item loop: loop-invariant values would stay
+  // live across the body)
+  const int it_ = ItemWalk(a.nitems).item(0);
+  if (it_ < 0) return;
+  const int t = threadIdx.x;
+  const Item item = a.items[it_];
+  const MemberDesc& md = a.mem[item.member];
+  const int le = t / NP, n = t - le * NP;
+  const int e = item.e0 + le;
+  double s0 = 0.0, s1 = 0.0;
+  if (e < md.ne) {
+    const unsigned N = a.nnodes;
+    const unsigned g = (unsigned)(md.eoff + e) * NP + n;
+    const ElemCoord<D> ec = item_coord<D>(md, item, le);
+    const int idx[3] = {n % P1, (n / P1) % P1, D == 3 ? n / (P1 * P1) : 0};
+    const int iz = md.hoff + ec.c[D - 1] * P1 + idx[D - 1];
+    const double rd = a.bg_rd[iz] + (double)ld(U, N, V::RD, g);
+    const double rm = a.bg_rm[iz] + (double)ld(U, N, V::RM, g);
+    const double rr = RAIN ? a.bg_rr[iz] + (double)ld(U, N, V::RR, g) : 0.0;
+    const double irho = 1.0 / (rd + rm + rr);
+    double w = md.J;
 #pragma unroll
-      for (int j = 0; j < D; ++j) w *= a.w[idx[j]];
-      double vr = 0.0;
-      if (RAIN) vr = a.vr_mode == 0 ? a.vr_const : (rr > 0.0 ? a.vr_pref * pow(rr, 0.125) : 0.0);
+    for (int j = 0; j < D; ++j) w *= a.w[idx[j]];
+    double vr = 0.0;
+    if (RAIN) vr = a.vr_mode == 0 ? a.vr_const : (rr > 0.0 ? a.vr_pref * pow(rr, 0.125) : 0.0);
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        const double ui = (double)ld(U, N, V::M0 + i, g) * irho;
-        const double ur = (i == D - 1) ? ui - vr : ui;
-        s0 += w * ui * ui;
-        s1 += w * ur * ur;
-      }
+    for (int i = 0; i < D; ++i) {
+      const double ui = (double)ld(U, N, V::M0 + i, g) * irho;
+      const double ur = (i == D - 1) ? ui - vr : ui;
+      s0 += w * ui * ui;
+      s1 += w * ur * ur;
     }
-    sm[0][t] = s0;
-    sm[1][t] = s1;
-    __syncthreads();
-    // fixed-order tree over the element's nodes
-    for (int h = 1; h < NP; h <<= 1) {
-      if ((n % (2 * h)) == 0 && n + h < NP) {
-        sm[0][t] += sm[0][t + h];
-        sm[1][t] += sm[1][t + h];
-      }
-      __syncthreads();
-    }
-    if (n == 0 && e < md.ne) {
-      a.sip_aK[md.eoff + e] = md.sip_pre * sqrt(sm[0][t]);
-      a.sip_aK[a.etot + md.eoff + e] = md.sip_pre * sqrt(sm[1][t]);
+  }
+  sm[0][t] = s0;
+  sm[1][t] = s1;
+  __syncthreads();
+  // fixed-order tree over the element's nodes
+  for (int h = 1; h < NP; h <<= 1) {
+    if ((n % (2 * h)) == 0 && n + h < NP) {
+      sm[0][t] += sm[0][t + h];
+      sm[1][t] += sm[1][t + h];
     }
     __syncthreads();
+  }
+  if (n == 0 && e < md.ne) {
+    a.sip_aK[md.eoff + e] = md.sip_pre * sqrt(sm[0][t]);
+    a.sip_aK[a.etot + md.eoff + e] = md.sip_pre * sqrt(sm[1][t]);
   }
 }
 
@@ -140,194 +138,191 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
   }
   R* out = (R*)a.sip_out;
   const int epb = (int)blockDim.x / NP;
-  const ItemWalk walk(a.nitems);
-#pragma clang loop unroll(disable)
-  for (int kk = 0;; ++kk) {
-    const int it_ = walk.item(kk);
-    if (it_ < 0) break;
-    const Item item = a.items[it_];
-    const MemberDesc& md = a.mem[item.member];
-    const unsigned N = a.nnodes;
-    const int le = t / NP, n = t - le * NP;
-    const int e = item.e0 + le;
-    const bool active = e < md.ne;
-    const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
-    const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
-    const int idx[3] = {n % P1, (n / P1) % P1, D == 3 ? n / (P1 * P1) : 0};
-    // A. the state, and the viscosity at the element's corners (vertex means)
+  // one work item per block (no item loop: loop-invariant values would stay
+  // live across the body)
+  const int it_ = ItemWalk(a.nitems).item(0);
+  if (it_ < 0) return;
+  const Item item = a.items[it_];
+  const MemberDesc& md = a.mem[item.member];
+  const unsigned N = a.nnodes;
+  const int le = t / NP, n = t - le * NP;
+  const int e = item.e0 + le;
+  const bool active = e < md.ne;
+  const unsigned g = (unsigned)(md.eoff + (active ? e : 0)) * NP + n;
+  const ElemCoord<D> ec = item_coord<D>(md, item, active ? le : 0);
+  const int idx[3] = {n % P1, (n / P1) % P1, D == 3 ? n / (P1 * P1) : 0};
+  // A. the state, and the viscosity at the element's corners (vertex means)
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sU[v * NT + t] = ld(U, N, v, g);
+    if (n < (1 << D)) {
+      long long vid = 0, stride = 1;
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        int va = ec.c[ax] + ((n >> ax) & 1);
+        if (md.bc[ax] == 0 && va == md.n[ax]) va = 0;
+        vid += va * stride;
+        stride *= md.nvx[ax];
+      }
+      sV[0][le][n] = a.sip_av[md.voff + vid];
+      sV[1][le][n] = a.sip_av[a.nvert + md.voff + vid];
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sU[v * NT + t] = R(0);
+  }
+  __syncthreads();
+  // the Q1 viscosity at the node
+  {
+    double a0 = 0.0, a1 = 0.0;
     if (active) {
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sU[v * NT + t] = ld(U, N, v, g);
-      if (n < (1 << D)) {
-        long long vid = 0, stride = 1;
+      for (int corner = 0; corner < (1 << D); ++corner) {
+        double wq = 1.0;
 #pragma unroll
         for (int ax = 0; ax < D; ++ax) {
-          int va = ec.c[ax] + ((n >> ax) & 1);
-          if (md.bc[ax] == 0 && va == md.n[ax]) va = 0;
-          vid += va * stride;
-          stride *= md.nvx[ax];
+          const double xi = a.xn[idx[ax]];
+          wq *= ((corner >> ax) & 1) ? 0.5 * (1.0 + xi) : 0.5 * (1.0 - xi);
         }
-        sV[0][le][n] = a.sip_av[md.voff + vid];
-        sV[1][le][n] = a.sip_av[a.nvert + md.voff + vid];
+        a0 += wq * sV[0][le][corner];
+        a1 += wq * sV[1][le][corner];
       }
+    }
+    sA[t] = (R)a0;
+    sA[NT + t] = (R)a1;
+  }
+  // B. gradients along each direction
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+    const int base = t - idx[j] * str;
+    const R dj = (R)md.two_over_h[j];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      R acc = R(0);
+#pragma unroll
+      for (int b = 0; b < P1; ++b) acc += sDm[idx[j] * P1 + b] * sU[v * NT + base + b * str];
+      sG[(j * NV + v) * NT + t] = dj * acc;
+    }
+  }
+  __syncthreads();
+  // C. face nodes: [U] and {G_j} across every interior face of the block,
+  // one variable at a time straight into LDS
+  for (int task = t; task < epb * NFE; task += (int)blockDim.x) {
+    const int fle = task / NFE;
+    const int r = task - fle * NFE;
+    const int f = r / NF;
+    const int fp = r - f * NF;
+    const int j = f >> 1, side = f & 1;
+    const int fe = item.e0 + fle;
+    bool live = fe < md.ne;
+    int en = 0;
+    if (live) {
+      const ElemCoord<D> fc = item_coord<D>(md, item, fle);
+      const int c = j == 0 ? fc.c[0] : (j == 1 ? fc.c[1] : fc.c[D - 1]);   // no dynamic private index
+      const bool at_end = side ? (c == md.n[j] - 1) : (c == 0);
+      live = !(at_end && md.bc[j] == 1);
+      int cn = side ? c + 1 : c - 1;
+      if (cn < 0) cn += md.n[j];
+      if (cn >= md.n[j]) cn -= md.n[j];
+      en = fe + (cn - c) * elem_stride(md, j);
+    }
+    // node of the line through face point fp at position 0 along j
+    // (fp enumerates the other axes, the lower one fastest)
+    int nf0;
+    if (D == 2) {
+      nf0 = (j == 0) ? fp * P1 : fp;
     } else {
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sU[v * NT + t] = R(0);
+      const int u = fp % P1, w2 = fp / P1;
+      nf0 = (j == 0) ? P1 * (u + P1 * w2) : (j == 1 ? u + P1 * P1 * w2 : u + P1 * w2);
     }
-    __syncthreads();
-    // the Q1 viscosity at the node
-    {
-      double a0 = 0.0, a1 = 0.0;
-      if (active) {
+    const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+    const int nown = fle * NP + nf0 + (side ? K : 0) * str;   // own face node (LDS index)
+    const int fnb = side ? 0 : K;                             // the neighbour's, along j
+    const unsigned gn0 = (unsigned)(md.eoff + en) * NP + nf0;
+    const R dj = (R)md.two_over_h[j];
 #pragma unroll
-        for (int corner = 0; corner < (1 << D); ++corner) {
-          double wq = 1.0;
+    for (int v = 0; v < NV; ++v) {
+      R ju = R(0), mg = R(0);
+      if (live) {
+        R gnb = R(0), unb = R(0);
 #pragma unroll
-          for (int ax = 0; ax < D; ++ax) {
-            const double xi = a.xn[idx[ax]];
-            wq *= ((corner >> ax) & 1) ? 0.5 * (1.0 + xi) : 0.5 * (1.0 - xi);
-          }
-          a0 += wq * sV[0][le][corner];
-          a1 += wq * sV[1][le][corner];
+        for (int b = 0; b < P1; ++b) {
+          const R ub = ld(U, N, v, gn0 + b * str);
+          gnb += sDm[fnb * P1 + b] * ub;
+          if (b == fnb) unb = ub;
         }
+        gnb *= dj;
+        const R uo = sU[v * NT + nown];
+        ju = side ? uo - unb : unb - uo;
+        mg = R(0.5) * (sG[(j * NV + v) * NT + nown] + gnb);
       }
-      sA[t] = (R)a0;
-      sA[NT + t] = (R)a1;
+      sJ[v * NFB + task] = ju;
+      sM[v * NFB + task] = mg;
     }
-    // B. gradients along each direction
+  }
+  __syncthreads();
+  // D. the tendency at every node.  The line coefficients d_j Dhat[i_j][a]
+  // alpha_a and the face coefficients depend on the viscosity field, not on
+  // the variable: they are formed once, then each variable reads only its
+  // gradients and face values.
+  if (active) {
+    constexpr int NA = RAIN ? 2 : 1;       // viscosity fields in use
+    R cw[NA][D][P1];                       // volume: d_j Dhat[i_j][a] alpha(line node a)
+    R cl[NA][D][2];                        // faces: d_j / w_{i_j} alpha_f, per side
+    R cd[D][2];                            // d_j / 2 D[f_j][i_j]
+    R ct[D];                               // tau_j
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
       const int base = t - idx[j] * str;
       const R dj = (R)md.two_over_h[j];
+      const R kw = dj / (R)a.w[idx[j]];
+      ct[j] = (R)md.sip_tau[j];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        R acc = R(0);
+      for (int b = 0; b < P1; ++b) {
+        const R db = dj * sDh[idx[j] * P1 + b];
 #pragma unroll
-        for (int b = 0; b < P1; ++b) acc += sDm[idx[j] * P1 + b] * sU[v * NT + base + b * str];
-        sG[(j * NV + v) * NT + t] = dj * acc;
+        for (int f = 0; f < NA; ++f) cw[f][j][b] = db * sA[f * NT + base + b * str];
+      }
+#pragma unroll
+      for (int side = 0; side < 2; ++side) {
+        const int fj = side ? K : 0;
+        cd[j][side] = R(0.5) * dj * sDm[fj * P1 + idx[j]];
+#pragma unroll
+        for (int f = 0; f < NA; ++f) cl[f][j][side] = kw * sA[f * NT + base + fj * str];
       }
     }
-    __syncthreads();
-    // C. face nodes: [U] and {G_j} across every interior face of the block,
-    // one variable at a time straight into LDS
-    for (int task = t; task < epb * NFE; task += (int)blockDim.x) {
-      const int fle = task / NFE;
-      const int r = task - fle * NFE;
-      const int f = r / NF;
-      const int fp = r - f * NF;
-      const int j = f >> 1, side = f & 1;
-      const int fe = item.e0 + fle;
-      bool live = fe < md.ne;
-      int en = 0;
-      if (live) {
-        const ElemCoord<D> fc = item_coord<D>(md, item, fle);
-        const int c = j == 0 ? fc.c[0] : (j == 1 ? fc.c[1] : fc.c[D - 1]);   // no dynamic private index
-        const bool at_end = side ? (c == md.n[j] - 1) : (c == 0);
-        live = !(at_end && md.bc[j] == 1);
-        int cn = side ? c + 1 : c - 1;
-        if (cn < 0) cn += md.n[j];
-        if (cn >= md.n[j]) cn -= md.n[j];
-        en = fe + (cn - c) * elem_stride(md, j);
-      }
-      // node of the line through face point fp at position 0 along j
-      // (fp enumerates the other axes, the lower one fastest)
-      int nf0;
-      if (D == 2) {
-        nf0 = (j == 0) ? fp * P1 : fp;
-      } else {
-        const int u = fp % P1, w2 = fp / P1;
-        nf0 = (j == 0) ? P1 * (u + P1 * w2) : (j == 1 ? u + P1 * P1 * w2 : u + P1 * w2);
-      }
-      const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
-      const int nown = fle * NP + nf0 + (side ? K : 0) * str;   // own face node (LDS index)
-      const int fnb = side ? 0 : K;                             // the neighbour's, along j
-      const unsigned gn0 = (unsigned)(md.eoff + en) * NP + nf0;
-      const R dj = (R)md.two_over_h[j];
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        R ju = R(0), mg = R(0);
-        if (live) {
-          R gnb = R(0), unb = R(0);
-#pragma unroll
-          for (int b = 0; b < P1; ++b) {
-            const R ub = ld(U, N, v, gn0 + b * str);
-            gnb += sDm[fnb * P1 + b] * ub;
-            if (b == fnb) unb = ub;
-          }
-          gnb *= dj;
-          const R uo = sU[v * NT + nown];
-          ju = side ? uo - unb : unb - uo;
-          mg = R(0.5) * (sG[(j * NV + v) * NT + nown] + gnb);
-        }
-        sJ[v * NFB + task] = ju;
-        sM[v * NFB + task] = mg;
-      }
-    }
-    __syncthreads();
-    // D. the tendency at every node.  The line coefficients d_j Dhat[i_j][a]
-    // alpha_a and the face coefficients depend on the viscosity field, not on
-    // the variable: they are formed once, then each variable reads only its
-    // gradients and face values.
-    if (active) {
-      constexpr int NA = RAIN ? 2 : 1;       // viscosity fields in use
-      R cw[NA][D][P1];                       // volume: d_j Dhat[i_j][a] alpha(line node a)
-      R cl[NA][D][2];                        // faces: d_j / w_{i_j} alpha_f, per side
-      R cd[D][2];                            // d_j / 2 D[f_j][i_j]
-      R ct[D];                               // tau_j
+#pragma unroll 1
+    for (int v = 0; v < NV; ++v) {
+      const bool rr = RAIN && v == V::RR;
+      R Sv = R(0);
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
         const int base = t - idx[j] * str;
-        const R dj = (R)md.two_over_h[j];
-        const R kw = dj / (R)a.w[idx[j]];
-        ct[j] = (R)md.sip_tau[j];
+        // volume
+        R acc = R(0);
 #pragma unroll
-        for (int b = 0; b < P1; ++b) {
-          const R db = dj * sDh[idx[j] * P1 + b];
-#pragma unroll
-          for (int f = 0; f < NA; ++f) cw[f][j][b] = db * sA[f * NT + base + b * str];
-        }
+        for (int b = 0; b < P1; ++b)
+          acc += (rr ? cw[NA - 1][j][b] : cw[0][j][b]) * sG[(j * NV + v) * NT + base + b * str];
+        Sv -= acc;
+        // faces: this node's line meets the minus face (side 0) and the plus face (side 1)
+        int fpj;
+        if (D == 2) fpj = (j == 0) ? idx[1] : idx[0];
+        else fpj = (j == 0) ? idx[1] + P1 * idx[2] : (j == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
           const int fj = side ? K : 0;
-          cd[j][side] = R(0.5) * dj * sDm[fj * P1 + idx[j]];
-#pragma unroll
-          for (int f = 0; f < NA; ++f) cl[f][j][side] = kw * sA[f * NT + base + fj * str];
+          const int task = le * NFE + (2 * j + side) * NF + fpj;
+          const R ju = sJ[v * NFB + task];
+          R term = cd[j][side] * ju;
+          if (idx[j] == fj) term += (side ? R(1) : R(-1)) * (sM[v * NFB + task] - ct[j] * ju);
+          Sv += (rr ? cl[NA - 1][j][side] : cl[0][j][side]) * term;
         }
       }
-#pragma unroll 1
-      for (int v = 0; v < NV; ++v) {
-        const bool rr = RAIN && v == V::RR;
-        R Sv = R(0);
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-          const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
-          const int base = t - idx[j] * str;
-          // volume
-          R acc = R(0);
-#pragma unroll
-          for (int b = 0; b < P1; ++b)
-            acc += (rr ? cw[NA - 1][j][b] : cw[0][j][b]) * sG[(j * NV + v) * NT + base + b * str];
-          Sv -= acc;
-          // faces: this node's line meets the minus face (side 0) and the plus face (side 1)
-          int fpj;
-          if (D == 2) fpj = (j == 0) ? idx[1] : idx[0];
-          else fpj = (j == 0) ? idx[1] + P1 * idx[2] : (j == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
-#pragma unroll
-          for (int side = 0; side < 2; ++side) {
-            const int fj = side ? K : 0;
-            const int task = le * NFE + (2 * j + side) * NF + fpj;
-            const R ju = sJ[v * NFB + task];
-            R term = cd[j][side] * ju;
-            if (idx[j] == fj) term += (side ? R(1) : R(-1)) * (sM[v * NFB + task] - ct[j] * ju);
-            Sv += (rr ? cl[NA - 1][j][side] : cl[0][j][side]) * term;
-          }
-        }
-        st(out, N, v, g, Sv);
-      }
+      st(out, N, v, g, Sv);
     }
-    __syncthreads();   // the tiles are reused by the next item
   }
 }
 
