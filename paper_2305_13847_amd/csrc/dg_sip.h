@@ -121,13 +121,12 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV, NT = S::NT;
   constexpr int NF = (D == 2) ? P1 : P1 * P1;          // nodes of one face
-  constexpr int NFE = 2 * D * NF;
-  constexpr int NFB = S::EPB * NFE;
+  constexpr int NFBJ = S::EPB * 2 * NF;                 // face points of one direction in a block
   __shared__ R sU[NV * NT];
-  __shared__ R sG[D * NV * NT];
+  __shared__ R sG[NV * NT];                  // one direction's gradients
   __shared__ R sA[2 * NT];
-  __shared__ R sJ[NV * NFB];
-  __shared__ R sM[NV * NFB];
+  __shared__ R sJ[NV * NFBJ];                // one direction's jumps [U]
+  __shared__ R sM[NV * NFBJ];                // and mean gradients {G_j}
   __shared__ R sDm[P1 * P1];
   __shared__ R sDh[P1 * P1];
   __shared__ double sV[2][S::EPB][1 << D];   // the viscosity at each element's corners
@@ -191,138 +190,141 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
     sA[t] = (R)a0;
     sA[NT + t] = (R)a1;
   }
-  // B. gradients along each direction
+  // B-D, one direction j at a time (the tiles hold one direction's
+  // gradients and face values, so a block needs a third of the LDS):
+  //   B. the gradient G_j of every variable at every node;
+  //   C. face points of the j-faces: [U] and {G_j}; the own side's gradient
+  //      from the state tile, the neighbour's from its normal line in HBM;
+  //   D. the volume and face terms of direction j at every node, added to
+  //      the tendency in the order j, volume, minus face, plus face.
+  R Sv[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Sv[v] = R(0);
+  constexpr int NFJ = 2 * NF;              // face points of one element's two j-faces
 #pragma unroll
   for (int j = 0; j < D; ++j) {
     const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
-    const int base = t - idx[j] * str;
     const R dj = (R)md.two_over_h[j];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R acc = R(0);
-#pragma unroll
-      for (int b = 0; b < P1; ++b) acc += sDm[idx[j] * P1 + b] * sU[v * NT + base + b * str];
-      sG[(j * NV + v) * NT + t] = dj * acc;
-    }
-  }
-  __syncthreads();
-  // C. face nodes: [U] and {G_j} across every interior face of the block,
-  // one variable at a time straight into LDS
-  for (int task = t; task < epb * NFE; task += (int)blockDim.x) {
-    const int fle = task / NFE;
-    const int r = task - fle * NFE;
-    const int f = r / NF;
-    const int fp = r - f * NF;
-    const int j = f >> 1, side = f & 1;
-    const int fe = item.e0 + fle;
-    bool live = fe < md.ne;
-    int en = 0;
-    if (live) {
-      const ElemCoord<D> fc = item_coord<D>(md, item, fle);
-      const int c = j == 0 ? fc.c[0] : (j == 1 ? fc.c[1] : fc.c[D - 1]);   // no dynamic private index
-      const bool at_end = side ? (c == md.n[j] - 1) : (c == 0);
-      live = !(at_end && md.bc[j] == 1);
-      int cn = side ? c + 1 : c - 1;
-      if (cn < 0) cn += md.n[j];
-      if (cn >= md.n[j]) cn -= md.n[j];
-      en = fe + (cn - c) * elem_stride(md, j);
-    }
-    // node of the line through face point fp at position 0 along j
-    // (fp enumerates the other axes, the lower one fastest)
-    int nf0;
-    if (D == 2) {
-      nf0 = (j == 0) ? fp * P1 : fp;
-    } else {
-      const int u = fp % P1, w2 = fp / P1;
-      nf0 = (j == 0) ? P1 * (u + P1 * w2) : (j == 1 ? u + P1 * P1 * w2 : u + P1 * w2);
-    }
-    const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
-    const int nown = fle * NP + nf0 + (side ? K : 0) * str;   // own face node (LDS index)
-    const int fnb = side ? 0 : K;                             // the neighbour's, along j
-    const unsigned gn0 = (unsigned)(md.eoff + en) * NP + nf0;
-    const R dj = (R)md.two_over_h[j];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R ju = R(0), mg = R(0);
-      if (live) {
-        R gnb = R(0), unb = R(0);
-#pragma unroll
-        for (int b = 0; b < P1; ++b) {
-          const R ub = ld(U, N, v, gn0 + b * str);
-          gnb += sDm[fnb * P1 + b] * ub;
-          if (b == fnb) unb = ub;
-        }
-        gnb *= dj;
-        const R uo = sU[v * NT + nown];
-        ju = side ? uo - unb : unb - uo;
-        mg = R(0.5) * (sG[(j * NV + v) * NT + nown] + gnb);
-      }
-      sJ[v * NFB + task] = ju;
-      sM[v * NFB + task] = mg;
-    }
-  }
-  __syncthreads();
-  // D. the tendency at every node.  The line coefficients d_j Dhat[i_j][a]
-  // alpha_a and the face coefficients depend on the viscosity field, not on
-  // the variable: they are formed once, then each variable reads only its
-  // gradients and face values.
-  if (active) {
-    constexpr int NA = RAIN ? 2 : 1;       // viscosity fields in use
-    R cw[NA][D][P1];                       // volume: d_j Dhat[i_j][a] alpha(line node a)
-    R cl[NA][D][2];                        // faces: d_j / w_{i_j} alpha_f, per side
-    R cd[D][2];                            // d_j / 2 D[f_j][i_j]
-    R ct[D];                               // tau_j
-#pragma unroll
-    for (int j = 0; j < D; ++j) {
-      const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
+    if (j > 0) __syncthreads();            // the previous direction's tiles are read
+    // B.
+    {
       const int base = t - idx[j] * str;
-      const R dj = (R)md.two_over_h[j];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        R acc = R(0);
+#pragma unroll
+        for (int b = 0; b < P1; ++b) acc += sDm[idx[j] * P1 + b] * sU[v * NT + base + b * str];
+        sG[v * NT + t] = dj * acc;
+      }
+    }
+    // C.
+    for (int task = t; task < epb * NFJ; task += (int)blockDim.x) {
+      const int fle = task / NFJ;
+      const int r = task - fle * NFJ;
+      const int side = r / NF;
+      const int fp = r - side * NF;
+      const int fe = item.e0 + fle;
+      bool live = fe < md.ne;
+      int en = 0;
+      if (live) {
+        const ElemCoord<D> fc = item_coord<D>(md, item, fle);
+        const int c = j == 0 ? fc.c[0] : (j == 1 ? fc.c[1] : fc.c[D - 1]);
+        const bool at_end = side ? (c == md.n[j] - 1) : (c == 0);
+        live = !(at_end && md.bc[j] == 1);
+        int cn = side ? c + 1 : c - 1;
+        if (cn < 0) cn += md.n[j];
+        if (cn >= md.n[j]) cn -= md.n[j];
+        en = fe + (cn - c) * elem_stride(md, j);
+      }
+      // node of the line through face point fp at position 0 along j
+      // (fp enumerates the other axes, the lower one fastest)
+      int nf0;
+      if (D == 2) {
+        nf0 = (j == 0) ? fp * P1 : fp;
+      } else {
+        const int u = fp % P1, w2 = fp / P1;
+        nf0 = (j == 0) ? P1 * (u + P1 * w2) : (j == 1 ? u + P1 * P1 * w2 : u + P1 * w2);
+      }
+      const int fo = side ? K : 0;                              // the own face node, along j
+      const int l0 = fle * NP + nf0;                            // the own line (LDS index)
+      const int fnb = side ? 0 : K;                             // the neighbour's, along j
+      const unsigned gn0 = (unsigned)(md.eoff + en) * NP + nf0;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        R ju = R(0), mg = R(0);
+        if (live) {
+          R gnb = R(0), unb = R(0), gow = R(0);
+#pragma unroll
+          for (int b = 0; b < P1; ++b) {
+            const R ub = ld(U, N, v, gn0 + b * str);
+            gnb += sDm[fnb * P1 + b] * ub;
+            if (b == fnb) unb = ub;
+            gow += sDm[fo * P1 + b] * sU[v * NT + l0 + b * str];
+          }
+          gnb *= dj;
+          gow *= dj;
+          const R uo = sU[v * NT + l0 + fo * str];
+          ju = side ? uo - unb : unb - uo;
+          mg = R(0.5) * (gow + gnb);
+        }
+        sJ[v * NFBJ + task] = ju;
+        sM[v * NFBJ + task] = mg;
+      }
+    }
+    __syncthreads();
+    // D.  The line coefficients d_j Dhat[i_j][a] alpha_a and the face
+    // coefficients depend on the viscosity field, not on the variable: they
+    // are formed once, then each variable reads only its gradients and face
+    // values.
+    if (active) {
+      constexpr int NA = RAIN ? 2 : 1;     // viscosity fields in use
+      R cw[NA][P1];                        // volume: d_j Dhat[i_j][a] alpha(line node a)
+      R cl[NA][2];                         // faces: d_j / w_{i_j} alpha_f, per side
+      R cd[2];                             // d_j / 2 D[f_j][i_j]
+      const int base = t - idx[j] * str;
       const R kw = dj / (R)a.w[idx[j]];
-      ct[j] = (R)md.sip_tau[j];
+      const R ct = (R)md.sip_tau[j];
 #pragma unroll
       for (int b = 0; b < P1; ++b) {
         const R db = dj * sDh[idx[j] * P1 + b];
 #pragma unroll
-        for (int f = 0; f < NA; ++f) cw[f][j][b] = db * sA[f * NT + base + b * str];
+        for (int f = 0; f < NA; ++f) cw[f][b] = db * sA[f * NT + base + b * str];
       }
 #pragma unroll
       for (int side = 0; side < 2; ++side) {
         const int fj = side ? K : 0;
-        cd[j][side] = R(0.5) * dj * sDm[fj * P1 + idx[j]];
+        cd[side] = R(0.5) * dj * sDm[fj * P1 + idx[j]];
 #pragma unroll
-        for (int f = 0; f < NA; ++f) cl[f][j][side] = kw * sA[f * NT + base + fj * str];
+        for (int f = 0; f < NA; ++f) cl[f][side] = kw * sA[f * NT + base + fj * str];
       }
-    }
-#pragma unroll 1
-    for (int v = 0; v < NV; ++v) {
-      const bool rr = RAIN && v == V::RR;
-      R Sv = R(0);
+      int fpj;
+      if (D == 2) fpj = (j == 0) ? idx[1] : idx[0];
+      else fpj = (j == 0) ? idx[1] + P1 * idx[2] : (j == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
 #pragma unroll
-      for (int j = 0; j < D; ++j) {
-        const int str = j == 0 ? 1 : (j == 1 ? P1 : P1 * P1);
-        const int base = t - idx[j] * str;
+      for (int v = 0; v < NV; ++v) {
+        const bool rr = RAIN && v == V::RR;
         // volume
         R acc = R(0);
 #pragma unroll
-        for (int b = 0; b < P1; ++b)
-          acc += (rr ? cw[NA - 1][j][b] : cw[0][j][b]) * sG[(j * NV + v) * NT + base + b * str];
-        Sv -= acc;
+        for (int b = 0; b < P1; ++b) acc += (rr ? cw[NA - 1][b] : cw[0][b]) * sG[v * NT + base + b * str];
+        R sv = Sv[v] - acc;
         // faces: this node's line meets the minus face (side 0) and the plus face (side 1)
-        int fpj;
-        if (D == 2) fpj = (j == 0) ? idx[1] : idx[0];
-        else fpj = (j == 0) ? idx[1] + P1 * idx[2] : (j == 1 ? idx[0] + P1 * idx[2] : idx[0] + P1 * idx[1]);
 #pragma unroll
         for (int side = 0; side < 2; ++side) {
           const int fj = side ? K : 0;
-          const int task = le * NFE + (2 * j + side) * NF + fpj;
-          const R ju = sJ[v * NFB + task];
-          R term = cd[j][side] * ju;
-          if (idx[j] == fj) term += (side ? R(1) : R(-1)) * (sM[v * NFB + task] - ct[j] * ju);
-          Sv += (rr ? cl[NA - 1][j][side] : cl[0][j][side]) * term;
+          const int task = le * NFJ + side * NF + fpj;
+          const R ju = sJ[v * NFBJ + task];
+          R term = cd[side] * ju;
+          if (idx[j] == fj) term += (side ? R(1) : R(-1)) * (sM[v * NFBJ + task] - ct * ju);
+          sv += (rr ? cl[NA - 1][side] : cl[0][side]) * term;
         }
+        Sv[v] = sv;
       }
-      st(out, N, v, g, Sv);
     }
+  }
+  if (active) {
+#pragma unroll
+    for (int v = 0; v < NV; ++v) st(out, N, v, g, Sv[v]);
   }
 }
 
