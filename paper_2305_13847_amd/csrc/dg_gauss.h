@@ -255,10 +255,16 @@ gauss_trace_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ 
 }
 
 // FP32 up to Q3 in 3D and Q5 in 2D: 4 wavefronts per SIMD (128 VGPRs; with
-// the face fluxes in the flux tile, four blocks fit a CU's LDS). Higher
-// orders and FP64 would spill there and are left to the compiler.
+// the face fluxes in the flux tile, four blocks fit a CU's LDS). FP64 up to
+// Q3 in 3D and Q6 in 2D: 2 wavefronts per SIMD, i.e. no more than 256
+// registers in all (left free, the compiler parks a few values in AGPRs
+// beyond the 256 VGPRs, which halves the occupancy). Higher orders would
+// spill under these bounds and are left to the compiler.
 template <typename R, int K, int D>
-constexpr int gauss_min_waves() { return (sizeof(R) == 4 && K <= (D == 3 ? 3 : 5)) ? 4 : 1; }
+constexpr int gauss_min_waves() {
+  if (sizeof(R) == 4) return K <= (D == 3 ? 3 : 5) ? 4 : 1;
+  return K <= (D == 3 ? 3 : 6) ? 2 : 1;
+}
 
 template <typename R, int K, int D, int RAIN, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gauss_min_waves<R, K, D>())))
