@@ -218,9 +218,9 @@ dg_status dg_destroy(dg_handle* h);
 
 /* Launch geometry: elements per block (1 .. 256 / (k+1)^dim) and persistent
  * blocks per compute unit (0: one block per work item; n > 0: a grid of
- * n x CUs blocks that walk the work items; the right-hand-side kernels of the
- * Gauss basis always take one block per work item).  Not a hot call:
- * synchronises. */
+ * n x CUs blocks that walk the work items).  Persistence applies to the
+ * Lobatto-basis stage kernel of dg_rk_step only; every other kernel takes
+ * one block per work item.  Not a hot call: synchronises. */
 dg_status dg_set_launch(dg_handle* h, int elems_per_block, int persist_per_cu);
 dg_status dg_get_launch(const dg_handle* h, int* elems_per_block, int* persist_per_cu);
 

@@ -102,10 +102,10 @@ split_kernel(KArgs a, int item0, int nitems, const R* __restrict__ U, const doub
   using S = Shape<K, D, block_threads<R>()>;
   using V = Vars<D, RAIN>;
   constexpr int P1 = S::P1, NP = S::NP, NV = V::NV;
-  const ItemWalk walk(nitems);
-  for (int k = 0;; ++k) {
-  const int it_ = walk.item(k);
-  if (it_ < 0) break;
+  // one work item per block (no item loop: loop-invariant values would stay
+  // live across the body)
+  const int it_ = ItemWalk(nitems).item(0);
+  if (it_ < 0) return;
   const int t = threadIdx.x;
   const Item item = a.items[item0 + it_];
   const MemberDesc& md = a.mem[item.member];
@@ -148,7 +148,6 @@ split_kernel(KArgs a, int item0, int nitems, const R* __restrict__ U, const doub
     }
   }
   record_stats(a, iters, bad);
-  }
 }
 
 // ---------------------------------------------------------------------------

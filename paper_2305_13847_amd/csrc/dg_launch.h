@@ -55,7 +55,9 @@ struct Launch {
     if (nitems <= 0) return true;
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
-      dim3 grid(lc.grid), block(lc.threads);
+      // one block per work item whatever the persistence setting (the split
+      // kernel has no item loop)
+      dim3 grid(grid_for_items(nitems)), block(lc.threads);
       if (api)
         hipLaunchKernelGGL((split_kernel<R, K_, D_, R_, 1>), grid, block, 0, s, a, item0, nitems,
                            (const R*)U, guess, oT, o1, o2);
@@ -86,10 +88,13 @@ struct Launch {
         if (mode == 0) DGM_RHS(rhs_gauss_kernel, 0);
         else if (mode == 1) DGM_RHS(rhs_gauss_kernel, 1);
         else DGM_RHS(rhs_gauss_kernel, 2);
-      } else if (mode == 0) DGM_RHS(rhs_kernel, 0);
-      else if (mode == 1) DGM_RHS(rhs_kernel, 1);
-      else if (!persist) DGM_RHS(rhs_kernel, 2);
-      else
+      } else if (mode != 2 || !persist) {
+        // rhs_kernel takes one work item per block: the full grid
+        grid = dim3(grid_for_items(a.nitems));
+        if (mode == 0) DGM_RHS(rhs_kernel, 0);
+        else if (mode == 1) DGM_RHS(rhs_kernel, 1);
+        else DGM_RHS(rhs_kernel, 2);
+      } else
         hipLaunchKernelGGL((rhs_kernel_persistent<R, K_, D_, R_, 2>), grid, block, 0, s, a, a_dev, (const R*)U,
                            auxT, auxS, (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, flags);
 #undef DGM_RHS

@@ -127,3 +127,24 @@ def test_autotune_picks_a_valid_geometry(tmp_path):
     dg2 = lib.for_ensemble(cases, precision=1)
     rec2 = dg2.autotune(U, dt, cache=cache, key="ens")      # from the cache
     assert rec2["elems_per_block"] == rec["elems_per_block"]
+
+
+@pytest.mark.parametrize("basis,sip", [("lobatto", 0.0), ("gauss", 0.0), ("lobatto", 0.3)])
+def test_persistent_grid_covers_every_item(basis, sip):
+    # one element per block and one persistent block per CU: with 384
+    # elements the grid is smaller than the item count, so every kernel must
+    # either walk the items or be launched on the full grid
+    lib = _lib()
+    c = synth.warm_rain_3d(n=(8, 8, 6), order=3, seed=9, basis=basis)
+    print("case", basis, sip, c.digest(), flush=True)
+    outs = []
+    for persist in (0, 1):
+        dg = lib.for_case(c, precision=1, sip_gamma=sip)
+        dg.set_launch(1, persist)
+        U = torch.tensor(c.U, dtype=torch.float32, device="cuda")
+        R = dg.rhs(U).cpu().numpy()
+        T = dg.saturation_split(U)[0].cpu().numpy()
+        dg.rk_step(U, c.dt, 2)
+        outs.append((R, T, U.cpu().numpy()))
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
