@@ -112,8 +112,7 @@ typedef struct {
    * U[v][e][n] and the background arrays are then values at the Gauss
    * points, and face fluxes use the traces of U', T and rho_v along each
    * normal line.  With DG_BASIS_GAUSS the adjoint calls dg_rhs_vjp and
-   * dg_rk_step_vjp return DG_EUNSUPPORTED, and dg_reduce_mass leaves its
-   * wall-flux entry NaN. */
+   * dg_rk_step_vjp return DG_EUNSUPPORTED. */
   int basis;                  /* DG_BASIS_LOBATTO or DG_BASIS_GAUSS             */
   /* Artificial diffusion (Section 3.5), Lobatto basis only: the symmetric
    * interior penalty form on interior faces, with penalty
@@ -153,13 +152,16 @@ dg_status dg_create(const dg_mesh* mesh, int order, int nvars, const dg_params* 
 dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int order, int nvars,
                           const dg_params* p, dg_handle** out);
 
-/* Background state of member m (Section 2.3): HOST arrays of n_z (k+1)
- * doubles at the node heights.  rho_r may be NULL (taken as 0).  The
- * background pressure is computed on the device as the equation of state of
- * the split background state.  Must be called for every member before the
- * first hot call; synchronises the device. */
-dg_status dg_set_background(dg_handle* h, int member, const double* rho_d,
-                            const double* rho_m, const double* rho_r, const double* E);
+/* Background state of ensemble member `member` (0 for a single mesh): the
+ * hydrostatic state the unknowns are perturbations of (Section 2.3).  HOST
+ * arrays of n_z (k+1) doubles at the node heights, copied.  rho_r may be NULL
+ * (taken as 0).  The background pressure is computed on the device as the
+ * equation of state of the split background state.  Must be called for every
+ * member before the first hot call; synchronises the device.  DG_EINVAL for a
+ * bad member, a null array, a non-finite value or a state with no valid
+ * temperature. */
+dg_status dg_set_background(dg_handle* h, const double* rho_d, const double* rho_m,
+                            const double* rho_r, const double* E, int member);
 
 /* Element offset and element count of member m in the concatenated layout. */
 dg_status dg_member_offset(const dg_handle* h, int member, long long* elem_offset,
@@ -202,12 +204,24 @@ dg_status dg_saturation_split_vjp(dg_handle* h, const void* U, const double* T_b
 dg_status dg_rk_step_vjp(dg_handle* h, const void* U_n, const void* U_np1_bar, void* U_n_bar,
                          const double* dt, hipStream_t stream);
 
-/* Conservation diagnostics of member m (or of all members if m < 0), in FP64
- * with a fixed-order reduction: out3[0] = sum w J rho_d', out3[1] = sum w J
- * (rho_m' + rho_r'), out3[2] = instantaneous rain mass flux out through the
- * slip walls.  out3 is a HOST array; the call synchronises the stream. */
-dg_status dg_reduce_mass(dg_handle* h, int member, const void* U, double* out3,
-                         hipStream_t stream);
+/* Conservation diagnostics of the state U (all members), in FP64 with a
+ * fixed-order reduction over the quadrature of the basis:
+ *   out3[0] = sum w J rho_d'             (dry mass; conserved),
+ *   out3[1] = sum w J (rho_m' + rho_r')   (total water; changes only by the
+ *             rain that sediments through the slip walls, Section 2.1 rain
+ *             flux with the wall treatment of Section 3.2),
+ *   out3[2] = the instantaneous rain mass flux out through the slip walls,
+ *             sum over wall face points of w_f J_f rho_r v_r (out at the floor,
+ *             in at the lid); with the Gauss basis rho_r is the face trace.
+ * U is a device array in the state layout; out3 is a HOST array of 3
+ * doubles, written when the call returns (it synchronises the stream).
+ * DG_EINVAL for null pointers or a handle without background. */
+dg_status dg_reduce_mass(dg_handle* h, const void* U, double* out3, hipStream_t stream);
+
+/* dg_reduce_mass restricted to ensemble member `member` (DG_EINVAL if it does
+ * not exist). */
+dg_status dg_reduce_mass_member(dg_handle* h, const void* U, double* out3, int member,
+                                hipStream_t stream);
 
 /* Read the device status words (synchronises the device).  Returns DG_OK,
  * DG_ENOCONV or DG_ENONFINITE. */

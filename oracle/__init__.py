@@ -16,11 +16,15 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "dg_oracle.cpp")
 LIB = os.path.join(HERE, "libdgoracle.so")
+# a prebuilt copy of the reference (the mutation checks load deliberately
+# broken builds this way; it is never rebuilt from SRC)
+LIB_OVERRIDE = os.environ.get("DG_ORACLE_LIB")
 
 
-def build(openmp: bool = False) -> str:
-    """Compile the reference with -O2 and no fast-math."""
-    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-o", LIB, SRC]
+def build() -> str:
+    """Compile the reference with -O2 and no fast-math; its element loops use
+    OpenMP (the result does not depend on the thread count)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-fopenmp", "-o", LIB, SRC]
     subprocess.check_call(cmd)
     return LIB
 
@@ -47,15 +51,23 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-            build()
-        L = ct.CDLL(LIB)
+        if LIB_OVERRIDE:
+            L = ct.CDLL(LIB_OVERRIDE)
+        else:
+            if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+                build()
+            L = ct.CDLL(LIB)
         dp = ct.POINTER(ct.c_double)
         L.ora_default_params.argtypes = [ct.POINTER(OraParams)]
         L.ora_tables.argtypes = [ct.c_int, dp, dp, dp, dp]
         L.ora_gauss_tables.argtypes = [ct.c_int, dp, dp]
         L.ora_project.argtypes = [ct.c_void_p, dp, dp]
         L.ora_sip.argtypes = [ct.c_void_p, dp, dp, dp]
+        L.ora_sip_alpha.argtypes = [ct.c_void_p, dp, dp, dp]
+        L.ora_set_threads.argtypes = [ct.c_int]
+        L.ora_set_threads.restype = None
+        L.ora_get_threads.argtypes = []
+        L.ora_get_threads.restype = ct.c_int
         L.ora_esat.argtypes = [ct.POINTER(OraParams), ct.c_double]
         L.ora_esat.restype = ct.c_double
         L.ora_rho_vs.argtypes = [ct.POINTER(OraParams), ct.c_double]
@@ -244,6 +256,15 @@ class Oracle:
             raise ValueError("needs the Lobatto basis and sip_gamma > 0")
         return out
 
+    def sip_alpha(self, W: np.ndarray):
+        """Nodal viscosity (every variable but rho_r, and rho_r) from W's velocity."""
+        W = np.ascontiguousarray(W, dtype=np.float64)
+        a0 = np.zeros(W.shape[1:])
+        a1 = np.zeros(W.shape[1:])
+        if lib().ora_sip_alpha(self.h, _p(W), _p(a0), _p(a1)) != 0:
+            raise ValueError("needs the Lobatto basis and sip_gamma > 0")
+        return a0, a1
+
     def project(self, U: np.ndarray) -> np.ndarray:
         """Legendre coefficients of a state given at the Gauss points (modal basis)."""
         U = np.ascontiguousarray(U, dtype=np.float64)
@@ -256,3 +277,12 @@ class Oracle:
         it, mx, bad = ct.c_long(), ct.c_int(), ct.c_int()
         lib().ora_stats(self.h, ct.byref(it), ct.byref(mx), ct.byref(bad))
         return dict(iters_total=it.value, max_iters=mx.value, bad=bad.value)
+
+
+def set_threads(n: int) -> None:
+    """Threads of the reference's element loops (n < 1: all cores)."""
+    lib().ora_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().ora_get_threads())

@@ -41,6 +41,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <omp.h>
 
 namespace {
 
@@ -480,7 +481,13 @@ template <class R> void point_core(const Ctx& c, const R* Uq, R T, R rv, double 
 
 // Pointwise reconstruction (Section 3.4): the split of the full state at node
 // height iz, then point_core.
-template <class R> void pointwise(Ctx& c, const R* Uq, int iz, Point<R>& q) {
+struct SplitStats {
+  long iters_total = 0;
+  int max_iters = 0;
+  int bad = 0;
+};
+
+template <class R> void pointwise(Ctx& c, const R* Uq, int iz, Point<R>& q, SplitStats* st = nullptr) {
   const OraParams& P = c.P;
   int d = c.d;
   R rd = c.bg_rd[iz] + Uq[v_rd()];
@@ -496,9 +503,15 @@ template <class R> void pointwise(Ctx& c, const R* Uq, int iz, Point<R>& q) {
   int ok = 1, iters = 0;
   R T, rv;
   split(P, rd, rm, rr, re, &T, &rv, &ok, &iters);
-  c.iters_total += iters;
-  c.max_iters = std::max(c.max_iters, iters);
-  if (!ok) c.bad++;
+  if (st) {
+    st->iters_total += iters;
+    st->max_iters = std::max(st->max_iters, iters);
+    if (!ok) st->bad++;
+  } else {
+    c.iters_total += iters;
+    c.max_iters = std::max(c.max_iters, iters);
+    if (!ok) c.bad++;
+  }
   point_core(c, Uq, T, rv, c.bg_rd[iz], c.bg_rm[iz], P.rain ? c.bg_rr[iz] : 0.0, c.bg_E[iz],
              c.bg_p[iz], q);
 }
@@ -617,6 +630,7 @@ template <class R> void sip_add(const Ctx& c, const R* U, R* dU, const std::vect
   auto g_at = [&](int j, int v, int e, int n) -> R& { return G[((size_t)j * nv + v) * N + (long)e * np + n]; };
   for (int j = 0; j < d; ++j)
     for (int v = 0; v < nv; ++v)
+#pragma omp parallel for schedule(static)
       for (int e = 0; e < ne; ++e)
         for (int n = 0; n < np; ++n) {
           const int a = node_axis(n, j, p1);
@@ -631,6 +645,7 @@ template <class R> void sip_add(const Ctx& c, const R* U, R* dU, const std::vect
     return (2.0 / c.h[j]) * t.D[node_axis(q, j, p1) * p1 + node_axis(i, j, p1)];
   };
   const double sig = c.P.sip_sigma * k * k;
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < ne; ++e)
     for (int i = 0; i < np; ++i)
       for (int v = 0; v < nv; ++v) {
@@ -678,15 +693,36 @@ template <class R> void rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
   const int nv = c.nvars, np = c.np, ne = c.ne, d = c.d, k = c.k, p1 = k + 1;
   const long N = (long)ne * np;
   auto at = [&](int v, int e, int n) -> long { return (long)v * N + (long)e * np + n; };
+  // Loops over elements may run on several threads (OpenMP); every value is
+  // computed by the same arithmetic in the same order whatever the thread
+  // count, so the result does not depend on it.
   // 1. pointwise reconstruction + fluxes at every node
   std::vector<Point<R>> q(N);
-  std::vector<R> Uq(nv);
-  for (int e = 0; e < ne; ++e)
-    for (int n = 0; n < np; ++n) {
-      for (int v = 0; v < nv; ++v) Uq[v] = U[at(v, e, n)];
-      pointwise(c, Uq.data(), height_of(c, e, n), q[(long)e * np + n]);
+  {
+    SplitStats tot;
+#pragma omp parallel
+    {
+      SplitStats st;
+      std::vector<R> Uq(nv);
+#pragma omp for schedule(static)
+      for (int e = 0; e < ne; ++e)
+        for (int n = 0; n < np; ++n) {
+          for (int v = 0; v < nv; ++v) Uq[v] = U[at(v, e, n)];
+          pointwise(c, Uq.data(), height_of(c, e, n), q[(long)e * np + n], &st);
+        }
+#pragma omp critical
+      {
+        tot.iters_total += st.iters_total;
+        tot.max_iters = std::max(tot.max_iters, st.max_iters);
+        tot.bad += st.bad;
+      }
     }
+    c.iters_total += tot.iters_total;
+    c.max_iters = std::max(c.max_iters, tot.max_iters);
+    c.bad += tot.bad;
+  }
   // 2. volume term: sum_j (2/h_j) sum_a Dhat[i_j][a] F_j(node a on the j-line)
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < ne; ++e)
     for (int n = 0; n < np; ++n)
       for (int v = 0; v < nv; ++v) {
@@ -700,61 +736,96 @@ template <class R> void rhs(Ctx& c, const R* U, R* dU, double* wall_rain_flux) {
         }
         dU[at(v, e, n)] = acc;
       }
-  // 3. faces with normal +e_j between K- = e and K+ = its +j neighbour
-  std::vector<R> Um(nv), Up(nv), Fs(nv);
+  // 3. faces with normal +e_j between K- = e and K+ = its +j neighbour.  For
+  // a fixed j the iteration for e writes only the +j face nodes of e and the
+  // -j face nodes of its +j neighbour (or, at a bottom wall, of e itself), so
+  // no two iterations touch the same node.  The wall rain flux is summed
+  // afterwards in the loop order.
   double wflux = 0.0;
+  std::vector<double> wtop, wbot;
+  if (c.P.rain) {
+    wtop.assign((size_t)N, 0.0);
+    wbot.assign((size_t)N, 0.0);
+  }
   for (int j = 0; j < d; ++j) {
-    double liftK = (2.0 / c.h[j]) / c.tab.w[k];
-    double lift0 = (2.0 / c.h[j]) / c.tab.w[0];
-    bool wall = c.M.bc[j] == 1;
-    for (int e = 0; e < ne; ++e) {
-      int ej = elem_axis(c, e, j);
-      bool top = ej == c.M.n[j] - 1;
-      bool bottom = ej == 0;
-      for (int n = 0; n < np; ++n) {
-        if (node_axis(n, j, p1) != k) continue;     // nodes of e on its +j face
-        int nb = node_set_axis(n, j, 0, p1);        // matching node on the other side
-        // face weight times face Jacobian, for the boundary flux diagnostic
-        double wf = 1.0;
-        for (int a = 0; a < d; ++a)
-          if (a != j) wf *= c.tab.w[node_axis(n, a, p1)] * 0.5 * c.h[a];
-        for (int v = 0; v < nv; ++v) Um[v] = U[at(v, e, n)];
-        const Point<R>& qm = q[(long)e * np + n];
-        if (wall && top) {
-          // top wall: U+ is the ghost of U-; only K- is updated
-          ghost_state(c, Um.data(), j, Up.data());
-          Point<R> qg;
-          pointwise(c, Up.data(), height_of(c, e, n), qg);
-          lf_flux(c, qm, Um.data(), qg, Up.data(), j, Fs.data());
-          for (int v = 0; v < nv; ++v) dU[at(v, e, n)] -= liftK * Fs[v];
-          if (c.P.rain) wflux += wf * val(Fs[v_rr(c)]);
-        } else {
-          int e2 = elem_shift(c, e, j, +1);
-          for (int v = 0; v < nv; ++v) Up[v] = U[at(v, e2, nb)];
-          const Point<R>& qp = q[(long)e2 * np + nb];
-          lf_flux(c, qm, Um.data(), qp, Up.data(), j, Fs.data());
-          for (int v = 0; v < nv; ++v) {
-            dU[at(v, e, n)] -= liftK * Fs[v];
-            dU[at(v, e2, nb)] += lift0 * Fs[v];
+    const double liftK = (2.0 / c.h[j]) / c.tab.w[k];
+    const double lift0 = (2.0 / c.h[j]) / c.tab.w[0];
+    const bool wall = c.M.bc[j] == 1;
+    SplitStats tot;
+#pragma omp parallel
+    {
+      SplitStats st;
+      std::vector<R> Um(nv), Up(nv), Fs(nv), Ui(nv), Ug(nv);
+#pragma omp for schedule(static)
+      for (int e = 0; e < ne; ++e) {
+        const int ej = elem_axis(c, e, j);
+        const bool top = ej == c.M.n[j] - 1;
+        const bool bottom = ej == 0;
+        for (int n = 0; n < np; ++n) {
+          if (node_axis(n, j, p1) != k) continue;     // nodes of e on its +j face
+          const int nb = node_set_axis(n, j, 0, p1);  // matching node on the other side
+          // face weight times face Jacobian, for the boundary flux diagnostic
+          double wf = 1.0;
+          for (int a = 0; a < d; ++a)
+            if (a != j) wf *= c.tab.w[node_axis(n, a, p1)] * 0.5 * c.h[a];
+          for (int v = 0; v < nv; ++v) Um[v] = U[at(v, e, n)];
+          const Point<R>& qm = q[(long)e * np + n];
+          if (wall && top) {
+            // top wall: U+ is the ghost of U-; only K- is updated
+            ghost_state(c, Um.data(), j, Up.data());
+            Point<R> qg;
+            pointwise(c, Up.data(), height_of(c, e, n), qg, &st);
+            lf_flux(c, qm, Um.data(), qg, Up.data(), j, Fs.data());
+            for (int v = 0; v < nv; ++v) dU[at(v, e, n)] -= liftK * Fs[v];
+            if (c.P.rain) wtop[(long)e * np + n] = wf * val(Fs[v_rr(c)]);
+          } else {
+            const int e2 = elem_shift(c, e, j, +1);
+            for (int v = 0; v < nv; ++v) Up[v] = U[at(v, e2, nb)];
+            const Point<R>& qp = q[(long)e2 * np + nb];
+            lf_flux(c, qm, Um.data(), qp, Up.data(), j, Fs.data());
+            for (int v = 0; v < nv; ++v) {
+              dU[at(v, e, n)] -= liftK * Fs[v];
+              dU[at(v, e2, nb)] += lift0 * Fs[v];
+            }
+          }
+          if (wall && bottom) {
+            // bottom wall of e: K- is the ghost below, K+ = e at its node index 0
+            const int n0 = node_set_axis(n, j, 0, p1);
+            for (int v = 0; v < nv; ++v) Ui[v] = U[at(v, e, n0)];
+            ghost_state(c, Ui.data(), j, Ug.data());
+            Point<R> qg;
+            pointwise(c, Ug.data(), height_of(c, e, n0), qg, &st);
+            const Point<R>& qi = q[(long)e * np + n0];
+            lf_flux(c, qg, Ug.data(), qi, Ui.data(), j, Fs.data());
+            for (int v = 0; v < nv; ++v) dU[at(v, e, n0)] += lift0 * Fs[v];
+            if (c.P.rain) wbot[(long)e * np + n] = wf * val(Fs[v_rr(c)]);
           }
         }
-        if (wall && bottom) {
-          // bottom wall of e: K- is the ghost below, K+ = e at its node index 0
-          int n0 = node_set_axis(n, j, 0, p1);
-          std::vector<R> Ui(nv), Ug(nv);
-          for (int v = 0; v < nv; ++v) Ui[v] = U[at(v, e, n0)];
-          ghost_state(c, Ui.data(), j, Ug.data());
-          Point<R> qg;
-          pointwise(c, Ug.data(), height_of(c, e, n0), qg);
-          const Point<R>& qi = q[(long)e * np + n0];
-          lf_flux(c, qg, Ug.data(), qi, Ui.data(), j, Fs.data());
-          for (int v = 0; v < nv; ++v) dU[at(v, e, n0)] += lift0 * Fs[v];
-          if (c.P.rain) wflux -= wf * val(Fs[v_rr(c)]);
-        }
+      }
+#pragma omp critical
+      {
+        tot.iters_total += st.iters_total;
+        tot.max_iters = std::max(tot.max_iters, st.max_iters);
+        tot.bad += st.bad;
       }
     }
+    c.iters_total += tot.iters_total;
+    c.max_iters = std::max(c.max_iters, tot.max_iters);
+    c.bad += tot.bad;
+    if (c.P.rain && wall)
+      for (int e = 0; e < ne; ++e) {
+        const int ej = elem_axis(c, e, j);
+        const bool top = ej == c.M.n[j] - 1, bottom = ej == 0;
+        if (!top && !bottom) continue;
+        for (int n = 0; n < np; ++n) {
+          if (node_axis(n, j, p1) != k) continue;
+          if (top) wflux += wtop[(long)e * np + n];
+          if (bottom) wflux -= wbot[(long)e * np + n];
+        }
+      }
   }
   // 4. sources
+#pragma omp parallel for schedule(static)
   for (int e = 0; e < ne; ++e)
     for (int n = 0; n < np; ++n)
       for (int v = 0; v < nv; ++v) dU[at(v, e, n)] += q[(long)e * np + n].G[v];
@@ -1074,21 +1145,28 @@ template <class R> void rk_step(Ctx& c, R* U, double dt, int scheme, double* out
     // u1 = u0 + dt/2 L(u0); u2 = u1 + dt/2 L(u1);
     // u3 = 2/3 u0 + 1/3 u2 + dt/6 L(u2); u4 = u3 + dt/2 L(u3)
     any_rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = u0[i] + (0.5 * dt) * L[i];
     any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = us[i] + (0.5 * dt) * L[i];
     any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = (2.0 / 3.0) * u0[i] + (1.0 / 3.0) * us[i] + (dt / 6.0) * L[i];
     any_rhs(c, us.data(), L.data(), &f); fl += f / 2.0;
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) U[i] = us[i] + (0.5 * dt) * L[i];
   } else {
     // u1 = u0 + dt L(u0); u2 = 3/4 u0 + 1/4 u1 + dt/4 L(u1);
     // u3 = 1/3 u0 + 2/3 u2 + 2/3 dt L(u2)
     any_rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = u0[i] + dt * L[i];
     any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = 0.75 * u0[i] + 0.25 * us[i] + (0.25 * dt) * L[i];
     any_rhs(c, us.data(), L.data(), &f); fl += f * (2.0 / 3.0);
+#pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) U[i] = (1.0 / 3.0) * u0[i] + (2.0 / 3.0) * us[i] + ((2.0 / 3.0) * dt) * L[i];
   }
   any_sponge(c, U);
@@ -1376,6 +1454,31 @@ int ora_sip(void* h, const double* U, const double* W, double* out) {
   sip_add(*c, U, out, an);
   return 0;
 }
+
+// The nodal viscosity of Section 3.5 from the velocities of the state W
+// (Lobatto basis, sip_gamma > 0): a0 for every variable but rho_r, a1 for
+// rho_r, one value per node in W's node order
+int ora_sip_alpha(void* h, const double* W, double* a0, double* a1) {
+  Ctx* c = (Ctx*)h;
+  if (c->basis != 0 || !(c->P.sip_gamma > 0.0)) return -1;
+  const long N = (long)c->ne * c->np;
+  std::vector<Point<double>> q(N);
+  std::vector<double> Wq(c->nvars);
+  for (int e = 0; e < c->ne; ++e)
+    for (int n = 0; n < c->np; ++n) {
+      for (int v = 0; v < c->nvars; ++v) Wq[v] = W[(long)v * N + (long)e * c->np + n];
+      pointwise(*c, Wq.data(), height_of(*c, e, n), q[(long)e * c->np + n]);
+    }
+  std::vector<double> an[2];
+  sip_alpha(*c, q, an);
+  std::copy(an[0].begin(), an[0].end(), a0);
+  std::copy(an[1].begin(), an[1].end(), a1);
+  return 0;
+}
+
+// Threads of the element loops (OpenMP); n < 1 restores the default.
+void ora_set_threads(int n) { omp_set_num_threads(n > 0 ? n : omp_get_num_procs()); }
+int ora_get_threads(void) { return omp_get_max_threads(); }
 
 // Legendre coefficients (the L2 projection by the Gauss rule) of a state given
 // at the Gauss points; modal basis only

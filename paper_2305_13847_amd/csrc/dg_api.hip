@@ -701,8 +701,8 @@ __global__ void bg_face_kernel(KArgs a, int K, int r0, int nrows, int rain) {
   bgf[4 * a.bgf_n + at] = (t[0] * a.Rd + t[5] * a.Rv) * t[4];
 }
 
-extern "C" dg_status dg_set_background(dg_handle* h, int member, const double* rd, const double* rm,
-                                       const double* rr, const double* E) {
+extern "C" dg_status dg_set_background(dg_handle* h, const double* rd, const double* rm, const double* rr,
+                                       const double* E, int member) {
   if (!h) return fail(DG_EINVAL, "null handle");
   if (member < 0 || member >= h->nmembers) return fail(DG_EINVAL, "bad member index %d", member);
   if (!rd || !rm || !E) return fail(DG_EINVAL, "null background array");
@@ -910,7 +910,7 @@ __global__ void reduce_partials_kernel(const double* partial, int n, double* out
     for (int c = 0; c < 3; ++c) out[c] = sm[c][0];
 }
 
-extern "C" dg_status dg_reduce_mass(dg_handle* h, int member, const void* U, double* out3, hipStream_t s) {
+static dg_status reduce_mass(dg_handle* h, int member, const void* U, double* out3, hipStream_t s) {
   dg_status st = ready(h);
   if (st != DG_OK) return st;
   if (!U || !out3) return fail(DG_EINVAL, "null pointer");
@@ -927,8 +927,17 @@ extern "C" dg_status dg_reduce_mass(dg_handle* h, int member, const void* U, dou
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(out3, h->red_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (h->P.basis != DG_BASIS_LOBATTO) out3[2] = std::nan("");   // no node layer on the wall
   return DG_OK;
+}
+
+extern "C" dg_status dg_reduce_mass(dg_handle* h, const void* U, double* out3, hipStream_t s) {
+  return reduce_mass(h, -1, U, out3, s);
+}
+
+extern "C" dg_status dg_reduce_mass_member(dg_handle* h, const void* U, double* out3, int member,
+                                           hipStream_t s) {
+  if (h && (member < 0 || member >= h->nmembers)) return fail(DG_EINVAL, "bad member index %d", member);
+  return reduce_mass(h, member, U, out3, s);
 }
 
 extern "C" dg_status dg_get_stats(dg_handle* h, dg_stats* out) {

@@ -835,15 +835,28 @@ mass_kernel(KArgs a, int item0, const R* __restrict__ U, double* __restrict__ pa
     for (int j = 0; j < D; ++j) w *= a.w[idx[j]];
     md_ = w * (double)U[V::RD * N + g];
     mw = w * ((double)U[V::RM * N + g] + (RAIN ? (double)U[V::RR * N + g] : 0.0));
-    // (Lobatto nodes only: the wall is a node layer there)
-    if (RAIN && md.bc[D - 1] == 1 && a.basis == 0) {
+    // rain through the slip walls: with Lobatto nodes the wall is a node
+    // layer; with Gauss nodes the thread of the lowest (highest) node of each
+    // vertical line takes the trace of rho_r' along it at the floor (lid),
+    // plus the background's face trace
+    if (RAIN && md.bc[D - 1] == 1) {
       const ElemCoord<D> ec = item_coord<D>(md, item, le);
       const int l = idx[D - 1];
       const bool bottom = ec.c[D - 1] == 0 && l == 0;
       const bool top = ec.c[D - 1] == md.n[D - 1] - 1 && l == K;
       if (bottom || top) {
-        const int iz = md.hoff + ec.c[D - 1] * P1 + l;
-        const double rr = a.bg_rr[iz] + (double)U[V::RR * N + g];
+        double rr;
+        if (a.basis == 0) {
+          rr = a.bg_rr[md.hoff + ec.c[D - 1] * P1 + l] + (double)U[V::RR * N + g];
+        } else {
+          constexpr int ZS = (D == 2) ? P1 : P1 * P1;   // node stride along the vertical
+          const double* Lt = bottom ? a.gl_m : a.gl_p;
+          const size_t g0 = g - (size_t)l * ZS;
+          double tr = 0.0;
+          for (int m = 0; m < P1; ++m) tr += Lt[m] * (double)U[V::RR * N + g0 + (size_t)m * ZS];
+          const int row = md.hoff / P1 + ec.c[D - 1];
+          rr = a.bgf[2 * a.bgf_n + 2 * row + (bottom ? 0 : 1)] + tr;
+        }
         double vr = a.vr_const;
         if (a.vr_mode != 0) vr = rr > 0.0 ? a.vr_pref * pow(rr, 0.125) : 0.0;
         double wf = md.face_J[D - 1];

@@ -55,7 +55,7 @@ class dg_stats(ct.Structure):
 
 EXPORTS = ["dg_default_params", "dg_create", "dg_create_batch", "dg_set_background",
            "dg_member_offset", "dg_state_size", "dg_rhs", "dg_saturation_split", "dg_rk_step",
-           "dg_rhs_vjp", "dg_saturation_split_vjp", "dg_rk_step_vjp", "dg_reduce_mass",
+           "dg_rhs_vjp", "dg_saturation_split_vjp", "dg_rk_step_vjp", "dg_reduce_mass", "dg_reduce_mass_member",
            "dg_get_stats", "dg_reset_stats", "dg_destroy", "dg_last_error", "dg_timing_enable",
            "dg_timing_read", "dg_set_launch", "dg_get_launch", "dg_autotune", "dg_rk_step_graph"]
 DG_K_SPLIT, DG_K_STAGE, DG_K_ADJOINT, DG_K_OTHER = 0, 1, 2, 3
@@ -77,7 +77,7 @@ def load(path: str = LIB_PATH):
     L.dg_create.argtypes = [ct.POINTER(dg_mesh), ct.c_int, ct.c_int, ct.POINTER(dg_params), ct.POINTER(vp)]
     L.dg_create_batch.argtypes = [ct.POINTER(dg_mesh), ct.c_int, ct.c_int, ct.c_int, ct.POINTER(dg_params),
                                   ct.POINTER(vp)]
-    L.dg_set_background.argtypes = [vp, ct.c_int, dp, dp, dp, dp]
+    L.dg_set_background.argtypes = [vp, dp, dp, dp, dp, ct.c_int]
     L.dg_member_offset.argtypes = [vp, ct.c_int, ct.POINTER(ct.c_longlong), ct.POINTER(ct.c_longlong)]
     L.dg_state_size.argtypes = [vp]
     L.dg_state_size.restype = ct.c_longlong
@@ -87,7 +87,8 @@ def load(path: str = LIB_PATH):
     L.dg_rhs_vjp.argtypes = [vp, vp, vp, vp, vp]
     L.dg_saturation_split_vjp.argtypes = [vp, vp, vp, vp, vp, vp, vp]
     L.dg_rk_step_vjp.argtypes = [vp, vp, vp, vp, dp, vp]
-    L.dg_reduce_mass.argtypes = [vp, ct.c_int, vp, dp, vp]
+    L.dg_reduce_mass.argtypes = [vp, vp, dp, vp]
+    L.dg_reduce_mass_member.argtypes = [vp, vp, dp, ct.c_int, vp]
     L.dg_get_stats.argtypes = [vp, ct.POINTER(dg_stats)]
     L.dg_reset_stats.argtypes = [vp]
     L.dg_destroy.argtypes = [vp]
@@ -202,8 +203,9 @@ class DG:
         for x in a + ([rr] if rr is not None else []):
             if x.size != nzq:
                 raise ValueError("background arrays need %d values" % nzq)
-        _check(self.L.dg_set_background(self.h, member, a[0].ctypes.data_as(dp), a[1].ctypes.data_as(dp),
-                                        None if rr is None else rr.ctypes.data_as(dp), a[2].ctypes.data_as(dp)))
+        _check(self.L.dg_set_background(self.h, a[0].ctypes.data_as(dp), a[1].ctypes.data_as(dp),
+                                        None if rr is None else rr.ctypes.data_as(dp), a[2].ctypes.data_as(dp),
+                                        int(member)))
 
     def rhs(self, U, out=None, stream=None):
         import torch
@@ -304,9 +306,14 @@ class DG:
         return out
 
     def reduce_mass(self, U, member: int = -1, stream=None):
+        """(dry mass, total water, wall rain outflow) of all members, or of one."""
         out = np.zeros(3)
-        _check(self.L.dg_reduce_mass(self.h, int(member), self._state(U),
-                                     out.ctypes.data_as(ct.POINTER(ct.c_double)), ct.c_void_p(_stream(stream))))
+        o = out.ctypes.data_as(ct.POINTER(ct.c_double))
+        if member < 0:
+            _check(self.L.dg_reduce_mass(self.h, self._state(U), o, ct.c_void_p(_stream(stream))))
+        else:
+            _check(self.L.dg_reduce_mass_member(self.h, self._state(U), o, int(member),
+                                                ct.c_void_p(_stream(stream))))
         return out
 
     def stats(self):

@@ -192,3 +192,106 @@ def test_branch_switching_steps(prec, tol):
     floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
     err = rel_l2(c.mesh, U.double().cpu().numpy().reshape(c.U.shape), ref, floor=floor)
     assert np.all(err < tol), err
+
+
+# ---------------------------------------------------------------------------
+# the COSMO terminal speed (Section 2.1): v_r = c rho_r^(1/8) at every point
+# ---------------------------------------------------------------------------
+COSMO_CASES = ["rain3d_q3", "rain3d_q2"]
+
+
+@pytest.mark.parametrize("name", COSMO_CASES)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-4)])
+def test_rhs_parity_cosmo_rain_speed(name, prec, tol):
+    c = CASES[name]()
+    print("case", name, prec, c.digest(), flush=True)
+    lib = _lib()
+    dg = lib.for_case(c, precision=prec, vr_mode=lib.DG_VR_COSMO)
+    dt = torch.float64 if prec == 0 else torch.float32
+    U = torch.tensor(c.U, dtype=dt, device="cuda").contiguous()
+    R = dg.rhs(U)
+    torch.cuda.synchronize()
+    o = O.Oracle.for_case(c, vr_mode=1)
+    ref = o.rhs(U.double().cpu().numpy().reshape(c.U.shape))
+    err = rel_max(R.double().cpu().numpy().reshape(c.U.shape), ref)
+    assert np.all(err < tol), err
+    # the speed differs from the constant one, so the mode is exercised
+    ref_const = O.Oracle.for_case(c).rhs(U.double().cpu().numpy().reshape(c.U.shape))
+    assert rel_max(ref, ref_const)[2] > 1e-3
+
+
+@pytest.mark.parametrize("name", COSMO_CASES)
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-4)])
+def test_ten_rk_steps_cosmo_rain_speed(name, prec, tol):
+    c = CASES[name]()
+    print("case", name, prec, c.digest(), flush=True)
+    lib = _lib()
+    dg = lib.for_case(c, precision=prec, vr_mode=lib.DG_VR_COSMO)
+    dt = torch.float64 if prec == 0 else torch.float32
+    U = torch.tensor(c.U, dtype=dt, device="cuda").contiguous()
+    dg.rk_step(U, c.dt, 10)
+    torch.cuda.synchronize()
+    ref, _ = O.Oracle.for_case(c, vr_mode=1).rk(c.U, c.dt, 10)
+    floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
+    err = rel_l2(c.mesh, U.double().cpu().numpy().reshape(c.U.shape), ref, floor=floor)
+    print("rel L2 per variable", err)
+    assert np.all(err < tol), err
+    st = dg.stats()
+    assert st["status"] == 0, st
+
+
+def test_mass_diagnostics_cosmo_rain_speed():
+    c = CASES["rain3d_q3"]()
+    lib = _lib()
+    dg = lib.for_case(c, precision=lib.DG_FP64, vr_mode=lib.DG_VR_COSMO)
+    U = torch.tensor(c.U, device="cuda")
+    m = dg.reduce_mass(U)
+    ref = O.Oracle.for_case(c, vr_mode=1).mass(c.U)
+    assert m[2] != 0.0 and m[2] == pytest.approx(ref[2], rel=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# Newton's iteration cap and the warm-started split of the boundary
+# ---------------------------------------------------------------------------
+def test_iteration_cap_is_reported():
+    # one Newton iteration cannot converge from the all-vapour temperature on
+    # saturated nodes: the kernel's own bounded loop ends and the status word
+    # says so
+    c = CASES["rain3d_q2"]()
+    lib = _lib()
+    dg = lib.for_case(c, precision=lib.DG_FP64, newton_maxit=1)
+    U = torch.tensor(c.U, device="cuda")
+    dg.saturation_split(U)
+    st = dg.stats()
+    assert st["status"] == lib.DG_ENOCONV and st["nonconverged"] > 0, st
+    assert st["max_iters"] == 1
+    dg.reset_stats()
+    dg.rk_step(U, c.dt, 1)
+    st = dg.stats()
+    assert st["status"] == lib.DG_ENOCONV and st["nonconverged"] > 0, st
+    # with the default cap the same state converges
+    dg2 = lib.for_case(c, precision=lib.DG_FP64)
+    dg2.saturation_split(torch.tensor(c.U, device="cuda"))
+    assert dg2.stats()["status"] == 0
+
+
+@pytest.mark.parametrize("name", ["rain3d_q3", "periodic2d"])
+def test_split_with_a_temperature_guess(name):
+    # the guess changes the iteration path only: any guess gives the root
+    c = CASES[name]()
+    lib = _lib()
+    dg, U = _gpu(c, lib.DG_FP64)
+    ref = O.Oracle.for_case(c).split_field(c.U)
+    Tref = ref["T"].reshape(-1)
+    rng = np.random.default_rng(3)
+    guesses = [Tref + rng.uniform(-0.5, 0.5, Tref.shape), Tref, np.full_like(Tref, 250.0),
+               np.full_like(Tref, 1.0e4), np.zeros_like(Tref)]
+    for gs in guesses:
+        T = torch.tensor(gs, device="cuda")
+        T, rv, rc = dg.saturation_split(U, T=T, use_guess=True)
+        torch.cuda.synchronize()
+        T = T.cpu().numpy().reshape(c.mesh.ne, c.mesh.npe)
+        rv = rv.cpu().numpy().reshape(c.mesh.ne, c.mesh.npe)
+        assert np.abs(T - ref["T"]).max() <= 1e-13 * ref["T"].max()
+        assert np.abs(rv - ref["rho_v"]).max() <= 1e-13 * ref["rho_v"].max()
+    assert dg.stats()["status"] == 0

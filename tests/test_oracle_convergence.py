@@ -29,13 +29,15 @@ def _run(f, k, n, tend, umax, L=10.0, cfl=0.2):
     return max(l2(mesh, U1[v] - Ue[v]) / l2(mesh, Ue[v]) for v in range(5) if l2(mesh, Ue[v]) > 0)
 
 
-@pytest.mark.parametrize("k,ns,min_rate", [(1, (8, 16, 32), 1.8), (2, (8, 16), 2.5),
-                                           (3, (8, 16), 3.8), (4, (4, 8), 4.5)])
-def test_moist_contact_order(k, ns, min_rate):
+@pytest.mark.parametrize("k,ns", [(1, (8, 16, 32)), (2, (16, 32, 64)), (3, (4, 8, 16)), (4, (4, 8, 16))])
+def test_moist_contact_order(k, ns):
+    # three levels: the rate over the two halvings is at least k + 1 - 0.3,
+    # and neither halving alone falls below k + 1 - 0.6
     f = lambda m, t: moist_contact(m, t, u0=(1000.0, 500.0))
     e = [_run(f, k, n, 0.25 * 10.0 / 1118.0, 1118.0 + 360.0) for n in ns]
-    rate = np.log2(e[-2] / e[-1])
-    assert rate > min_rate, (e, rate)
+    rates = np.log2(np.array(e[:-1]) / np.array(e[1:]))
+    overall = 0.5 * np.log2(e[0] / e[2])
+    assert overall >= k + 1 - 0.3 and rates.min() >= k + 1 - 0.6, (e, rates, overall)
 
 
 def test_vortex_order_q3():

@@ -160,3 +160,112 @@ def test_single_element_jump_is_the_penalty(k, walls):
     got = _form(o, mesh, U, U, W)
     nfaces = 3 if walls else 4
     assert got == pytest.approx(nfaces * sig * k * k * alpha, rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the viscosity field itself: element values alpha_K and their continuous Q1
+# carry by vertex means (hand-computed nodal values)
+# ---------------------------------------------------------------------------
+def _element_speeds_state(mesh, speeds, rain=False, w=0.0):
+    """State at rest but for a horizontal velocity constant on each element
+    (speeds[e]) and a uniform vertical velocity w."""
+    one = np.ones((mesh.ne, mesh.npe))
+    ux = np.asarray(speeds, float)[:, None] * one
+    rr = 1e-3 * one if rain else 0 * one
+    return conservative(mesh, 1.1 * one, 0.004 * one, 0 * one, rr, 285.0 * one, [ux, w * one], rain=rain)
+
+
+def _alpha_fields(mesh, speeds, gam=0.3, rain=False, w=0.0, vr=5.0):
+    W, bg = _element_speeds_state(mesh, speeds, rain=rain, w=w)
+    P = O.default_params(g=0.0, sip_gamma=gam, rain=1 if rain else 0, vr_const=vr)
+    o = O.Oracle(mesh, P, 6 if rain else 5, bg)
+    return o.sip_alpha(W)
+
+
+def _node_ref_coords(mesh):
+    x = O.tables(mesh.order)[0]
+    p1 = mesh.order + 1
+    n = np.arange(mesh.npe)
+    return x[n % p1], x[n // p1]
+
+
+def test_viscosity_carry_on_a_periodic_2x2_mesh_is_the_mean():
+    # every vertex of a 2 x 2 periodic mesh touches all four elements, so the
+    # continuous field is the mean of the four element values everywhere
+    L, gam = 2000.0, 0.3
+    mesh = periodic_mesh((2, 2), 3, L=L)
+    speeds = [1.0, 2.0, 3.0, 6.0]
+    a0, a1 = _alpha_fields(mesh, speeds, gam)
+    aK = gam * 0.5 * (L / 2) * np.asarray(speeds)        # 2D: ||u||_{0,K} = |u_K| h
+    np.testing.assert_allclose(a0, np.full_like(a0, aK.mean()), rtol=1e-13)
+    np.testing.assert_allclose(a1, a0, rtol=0)
+
+
+def test_viscosity_carry_with_walls_interpolates_the_row_means():
+    # periodic in x (2 columns), slip walls in z (2 rows): the vertices on the
+    # floor touch the bottom row only, the middle vertices all four elements,
+    # the lid vertices the top row only; in between, the Q1 interpolant is
+    # linear in the reference height
+    L, gam = 2000.0, 0.3
+    mesh = synth.Mesh(2, [2, 2], [0, 0], [L, L], [0, 1], 3)
+    speeds = [1.0, 2.0, 3.0, 6.0]                     # e = ex + 2 ez
+    a0, _ = _alpha_fields(mesh, speeds, gam)
+    c = gam * 0.5 * (L / 2)
+    floor, mid, lid = c * 1.5, c * 3.0, c * 4.5
+    _, eta = _node_ref_coords(mesh)
+    s = 0.5 * (1.0 + eta)
+    for e in range(4):
+        lo, hi = (floor, mid) if e < 2 else (mid, lid)
+        np.testing.assert_allclose(a0[e], (1.0 - s) * lo + s * hi, rtol=1e-13)
+    # corner and mid-edge values spelled out for the bottom-left element
+    p1 = mesh.order + 1
+    assert a0[0][0] == pytest.approx(floor, rel=1e-13)                  # floor corner
+    assert a0[0][p1 * mesh.order] == pytest.approx(mid, rel=1e-13)      # upper corner
+
+
+def test_viscosity_carry_on_a_periodic_3x3_mesh_by_geometry():
+    # vertex means found geometrically: a vertex at (X, Z) collects the elements
+    # whose closure contains it, with periodic images; the nodal value is the
+    # bilinear blend of the element's four corner means
+    L, gam, n, k = 3000.0, 0.3, 3, 2
+    mesh = periodic_mesh((n, n), k, L=L)
+    speeds = np.array([1.0, 5.0, 2.0, 7.0, 3.0, 4.0, 9.0, 6.0, 8.0])
+    a0, _ = _alpha_fields(mesh, speeds, gam)
+    h = L / n
+    aK = gam * 0.5 * h * speeds
+
+    def vertex_mean(X, Z):
+        vals = []
+        for e in range(mesh.ne):
+            ex, ez = e % n, e // n
+            for sx in (-L, 0.0, L):
+                for sz in (-L, 0.0, L):
+                    x0, z0 = ex * h + sx, ez * h + sz
+                    if x0 - 1e-9 <= X <= x0 + h + 1e-9 and z0 - 1e-9 <= Z <= z0 + h + 1e-9:
+                        vals.append(aK[e])
+        return np.mean(vals)
+
+    xi, eta = _node_ref_coords(mesh)
+    for e in range(mesh.ne):
+        ex, ez = e % n, e // n
+        corners = [[vertex_mean((ex + a) * h, (ez + b) * h) for a in (0, 1)] for b in (0, 1)]
+        s, t = 0.5 * (1 + xi), 0.5 * (1 + eta)
+        want = ((1 - s) * (1 - t) * corners[0][0] + s * (1 - t) * corners[0][1]
+                + (1 - s) * t * corners[1][0] + s * t * corners[1][1])
+        np.testing.assert_allclose(a0[e], want, rtol=1e-13)
+    # the vertex means are not all alike here, so the blend is exercised
+    assert np.ptp(a0) > 0.3 * np.ptp(aK)
+
+
+def test_rain_viscosity_uses_the_velocity_relative_to_the_falling_rain():
+    # u = (0, w) with w = 2 m/s upward and v_r = 5 m/s: the rain moves at
+    # u - v_r e_z, |2 - 5| = 3 m/s (not |2 + 5| = 7); the rest moves at 2 m/s
+    L, gam = 2000.0, 0.3
+    mesh = periodic_mesh((3, 3), 2, L=L)
+    a0, a1 = _alpha_fields(mesh, np.zeros(9), gam, rain=True, w=2.0, vr=5.0)
+    c = gam * 0.5 * (L / 3)
+    np.testing.assert_allclose(a0, np.full_like(a0, c * 2.0), rtol=1e-12)
+    np.testing.assert_allclose(a1, np.full_like(a1, c * 3.0), rtol=1e-12)
+    # downward air: |-2 - 5| = 7
+    a0, a1 = _alpha_fields(mesh, np.zeros(9), gam, rain=True, w=-2.0, vr=5.0)
+    np.testing.assert_allclose(a1, np.full_like(a1, c * 7.0), rtol=1e-12)
