@@ -175,6 +175,18 @@ long long dg_state_size(const dg_handle* h);
  * layout and precision; they must not alias. */
 dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t stream);
 
+/* dg_rhs for callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels, with the split's per-node scratch (T and rho_vs(T), 16 bytes per
+ * node) in a static device array of 32 MiB that the library holds on every
+ * GPU it runs on until the process ends, instead of the handle's buffers.
+ * The call allocates nothing.  Limits: at most 2^21 nodes (elements x nodes
+ * per element) per handle, otherwise DG_EINVAL; Lobatto basis without
+ * artificial diffusion, otherwise DG_EUNSUPPORTED.  All calls on one GPU
+ * share the array: calls that overlap in time on one GPU race, so the caller
+ * orders them (one stream, or events).  Arguments and results as dg_rhs. */
+dg_status dg_rhs_noalloc(dg_handle* h, const void* U, void* dUdt, hipStream_t stream);
+
 /* Implicit condensation split of Section 2.2 at every node: device double
  * arrays of one value per node (elements x nodes).  T is in/out: if
  * use_guess != 0 its contents seed Newton (warm start), otherwise it is

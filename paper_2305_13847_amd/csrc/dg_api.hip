@@ -10,6 +10,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 #include <tuple>
@@ -810,6 +811,59 @@ extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t
   if (h->sip) do_sip(h, U, s);
   do_gauss_trace(h, U, h->auxT, h->auxS, 0, s);
   do_rhs(h, 0, U, h->auxT, h->auxS, dUdt, nullptr, 0, 0, 0, s, nullptr, nullptr, h->sip ? kSip : 0, 0, 1);
+  HIP_TRY(hipGetLastError());
+  return DG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// right-hand side without allocation: the split scratch in a static array
+// ---------------------------------------------------------------------------
+// The split that precedes the right-hand side keeps (T, rho_vs(T)) per node
+// (16 bytes) between its two kernels.  dg_rhs keeps them in the handle's
+// buffers; dg_rhs_noalloc keeps them in this file-scope device array, of which
+// every GPU the library runs on holds its own copy until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is only
+// a stand-in): the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current.
+constexpr size_t kScratchBytes = size_t(32) << 20;
+constexpr long long kScratchNodes = (long long)(kScratchBytes / (2 * sizeof(double)));
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[64] = {};
+
+static dg_status scratch_for_current_device(void** out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(DG_EINVAL, "device ordinal %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(DG_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DG_OK;
+}
+
+extern "C" dg_status dg_rhs_noalloc(dg_handle* h, const void* U, void* dUdt, hipStream_t s) {
+  dg_status st = ready(h);
+  if (st != DG_OK) return st;
+  if (!U || !dUdt) return fail(DG_EINVAL, "null state pointer");
+  if (U == dUdt) return fail(DG_EINVAL, "U and dUdt must not alias");
+  if (h->P.basis != DG_BASIS_LOBATTO || h->sip)
+    return fail(DG_EUNSUPPORTED, "dg_rhs_noalloc covers the Lobatto basis without diffusion");
+  if (h->nnodes > kScratchNodes)
+    return fail(DG_EINVAL, "dg_rhs_noalloc holds at most %lld nodes in its %zu-byte scratch (handle has %lld)",
+                kScratchNodes, kScratchBytes, h->nnodes);
+  void* base = nullptr;
+  st = scratch_for_current_device(&base);
+  if (st != DG_OK) return st;
+  double* sT = (double*)base;
+  double* sS = sT + h->nnodes;
+  if (!do_split(h, U, nullptr, sT, sS, nullptr, 0, s)) return fail(DG_EUNSUPPORTED, "no kernel for this shape");
+  do_rhs(h, 0, U, sT, sS, dUdt, nullptr, 0, 0, 0, s);
   HIP_TRY(hipGetLastError());
   return DG_OK;
 }

@@ -57,7 +57,8 @@ EXPORTS = ["dg_default_params", "dg_create", "dg_create_batch", "dg_set_backgrou
            "dg_member_offset", "dg_state_size", "dg_rhs", "dg_saturation_split", "dg_rk_step",
            "dg_rhs_vjp", "dg_saturation_split_vjp", "dg_rk_step_vjp", "dg_reduce_mass", "dg_reduce_mass_member",
            "dg_get_stats", "dg_reset_stats", "dg_destroy", "dg_last_error", "dg_timing_enable",
-           "dg_timing_read", "dg_set_launch", "dg_get_launch", "dg_autotune", "dg_rk_step_graph"]
+           "dg_timing_read", "dg_set_launch", "dg_get_launch", "dg_autotune", "dg_rk_step_graph",
+           "dg_rhs_noalloc"]
 DG_K_SPLIT, DG_K_STAGE, DG_K_ADJOINT, DG_K_OTHER = 0, 1, 2, 3
 
 _lib = None
@@ -82,6 +83,7 @@ def load(path: str = LIB_PATH):
     L.dg_state_size.argtypes = [vp]
     L.dg_state_size.restype = ct.c_longlong
     L.dg_rhs.argtypes = [vp, vp, vp, vp]
+    L.dg_rhs_noalloc.argtypes = [vp, vp, vp, vp]
     L.dg_saturation_split.argtypes = [vp, vp, vp, ct.c_int, vp, vp, vp]
     L.dg_rk_step.argtypes = [vp, vp, dp, ct.c_int, vp]
     L.dg_rhs_vjp.argtypes = [vp, vp, vp, vp, vp]
@@ -212,6 +214,12 @@ class DG:
         if out is None:
             out = torch.empty_like(U)
         _check(self.L.dg_rhs(self.h, self._state(U), self._state(out, "dUdt"), ct.c_void_p(_stream(stream))))
+        return out
+
+    def rhs_noalloc(self, U, out, stream=None):
+        """dg_rhs with the split scratch in the library's static device array;
+        `out` must be given (nothing is allocated)."""
+        _check(self.L.dg_rhs_noalloc(self.h, self._state(U), self._state(out, "dUdt"), ct.c_void_p(_stream(stream))))
         return out
 
     def saturation_split(self, U, T=None, use_guess=False, stream=None):
