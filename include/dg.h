@@ -138,12 +138,15 @@ typedef struct {
 /* Fill *p with the paper's constants, no rain, FP64, SSPRK(4,3), no sponge. */
 void dg_default_params(dg_params* p);
 
-/* Create a handle for one mesh.  order k in 1..7 in 2D and 1..4 in 3D (a 3D
- * element of order 5 or more has more nodes than a thread block; one thread
- * owns one node), nvars = 3 + dim (rain = 0)
- * or 4 + dim (rain = 1), otherwise DG_EINVAL.  A handle holds fewer than
- * 2^29 nodes in FP64 and 2^30 in FP32 bulk (each variable's array stays below
- * 4 GiB), otherwise DG_EINVAL.  *out receives the handle. */
+/* Create a handle for one mesh (Section 3.1 space on the box, Section 3.2
+ * discretisation, with the model of Sections 2.1-2.3 in *p).  order k in 1..7
+ * in 2D and 1..4 in 3D (a 3D element of order 5 or more has more nodes than a
+ * thread block; one thread owns one node), nvars = 3 + dim (rain = 0) or
+ * 4 + dim (rain = 1), otherwise DG_EINVAL.  A handle holds fewer than 2^29
+ * nodes in FP64 and 2^30 in FP32 bulk (each variable's array stays below
+ * 4 GiB), otherwise DG_EINVAL.  Device memory for tables, stage buffers and status
+ * words is allocated here (DG_ENOMEM on failure).  *out receives the
+ * handle; release it with dg_destroy. */
 dg_status dg_create(const dg_mesh* mesh, int order, int nvars, const dg_params* p,
                     dg_handle** out);
 

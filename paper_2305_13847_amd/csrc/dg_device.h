@@ -122,6 +122,12 @@ constexpr double kShortX = 1.0e-4;
 __device__ __forceinline__ double rvs_near(const KArgs& a, const Anchor& A, double T, double* drvs) {
   const double x = (T - A.T0) * A.inv0;
   double l, q, e;
+  if (__all(x == 0.0)) {
+    // at the anchor itself (the first step of a warm-started solve): the
+    // series below give exactly these values for x = 0
+    *drvs = A.r0 * (a.am1 + a.b * A.inv0) * A.inv0;
+    return A.r0;
+  }
   if (__all(fabs(x) <= kShortX)) {
     l = x * (1.0 + x * (-0.5 + x * (1.0 / 3.0 - x * 0.25)));
     q = 1.0 + x * (-1.0 + x * (1.0 - x));
@@ -179,8 +185,10 @@ __device__ __forceinline__ NewtonOut newton_sat(const KArgs& a, double Cu, doubl
                                                 double Tu, double lo, double T, Anchor& A) {
   const double dc = a.cvv - a.cl;
   if (!(A.T0 > 0.0) || !in_anchor(A, T)) A = make_anchor(a, T);
+  // |dT| <= tol with tol = rtol T, or above 150 K max(rtol T, 2 sqrt(rtol T)),
+  // compared as squares
   const double tol_lin = a.rtol * T;
-  const double tol = T > 150.0 ? fmax(tol_lin, 2.0 * sqrt(tol_lin)) : tol_lin;
+  const double tol2 = T > 150.0 ? fmax(tol_lin * tol_lin, 4.0 * tol_lin) : tol_lin * tol_lin;
   NewtonOut o;
   o.state = 2;
   double rvs = 0.0;
@@ -195,7 +203,7 @@ __device__ __forceinline__ NewtonOut newton_sat(const KArgs& a, double Cu, doubl
     const double fp = Cv + drvs * (dc * Tm + a.Lp);
     const double dT = -f * __builtin_amdgcn_rcp(fp);
     ++it;
-    if (fabs(dT) <= tol) {
+    if (dT * dT <= tol2) {
       T += dT;
       rvs += drvs * dT;          // first order is exact to rounding for this step size
       o.state = 0;

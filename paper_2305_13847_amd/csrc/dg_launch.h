@@ -3,6 +3,7 @@
 #pragma once
 #include <type_traits>
 #include "dg_kernels.h"
+#include "dg_q3.h"
 #include "dg_gauss.h"
 #include "dg_sip.h"
 #include "dg_vjp.h"
@@ -88,6 +89,16 @@ struct Launch {
         if (mode == 0) DGM_RHS(rhs_gauss_kernel, 0);
         else if (mode == 1) DGM_RHS(rhs_gauss_kernel, 1);
         else DGM_RHS(rhs_gauss_kernel, 2);
+      } else if (K_ == 3 && D_ == 3) {
+        // Q3 hexahedra: one wavefront per element, one work item per block
+        // whatever the persistence setting (the kernel has no item loop)
+        grid = dim3(grid_for_items(a.nitems));
+        if (mode == 0) hipLaunchKernelGGL((rhs_q3_kernel<R, R_, 0>), grid, block, 0, s, a, (const R*)U, auxT, auxS,
+                                           (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, flags);
+        else if (mode == 1) hipLaunchKernelGGL((rhs_q3_kernel<R, R_, 1>), grid, block, 0, s, a, (const R*)U, auxT,
+                                                auxS, (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, flags);
+        else hipLaunchKernelGGL((rhs_q3_kernel<R, R_, 2>), grid, block, 0, s, a, (const R*)U, auxT, auxS,
+                                (R*)out, (const R*)U0, dt, c0, c1, c2, oT, oS, flags);
       } else if (mode != 2 || !persist) {
         // rhs_kernel takes one work item per block: the full grid
         grid = dim3(grid_for_items(a.nitems));
