@@ -173,9 +173,12 @@ dg_status dg_member_offset(const dg_handle* h, int member, long long* elem_offse
 /* Total number of values in one state array (nvars x elements x nodes). */
 long long dg_state_size(const dg_handle* h);
 
-/* dUdt = M^{-1} (volume + face + source terms) of Section 3.2, including the
- * pointwise split of Section 3.4.  U and dUdt: device arrays in the state
- * layout and precision; they must not alias. */
+/* dUdt = M^{-1} (volume + face + source terms) of the Section 3.2 weak form
+ * with the diagonal mass of Section 3.3, after the pointwise split of
+ * Section 3.4 (fluxes and sources of the Section 2.3 perturbation system,
+ * Kessler sources of Section 2.1 when rain is on).  U and dUdt: caller-owned
+ * device arrays in the state layout and precision; they must not alias
+ * (DG_EINVAL).  Uses the handle's split buffers. */
 dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t stream);
 
 /* dg_rhs for callers that cannot allocate device memory (code under graph
@@ -190,32 +193,49 @@ dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t stream);
  * orders them (one stream, or events).  Arguments and results as dg_rhs. */
 dg_status dg_rhs_noalloc(dg_handle* h, const void* U, void* dUdt, hipStream_t stream);
 
-/* Implicit condensation split of Section 2.2 at every node: device double
- * arrays of one value per node (elements x nodes).  T is in/out: if
- * use_guess != 0 its contents seed Newton (warm start), otherwise it is
- * output only.  rho_v or rho_c may be NULL. */
+/* Implicit condensation split of Section 2.2 at every node of U (the
+ * reconstruction of Section 3.4): T, rho_v = min(rho_vs(T), rho_m) and
+ * rho_c = rho_m - rho_v with rho e = E - |m|^2 / (2 rho).  T, rho_v, rho_c
+ * are caller-owned device double arrays of one value per node (elements x
+ * nodes, node order of U).  T is in/out: if use_guess != 0 its contents seed
+ * Newton (warm start; a guess outside (lower bound, 600 K) is ignored),
+ * otherwise it is output only.  rho_v or rho_c may be NULL.  DG_EINVAL for a
+ * null U or T; a solve that hits newton_maxit or a state with no valid
+ * temperature is reported by dg_get_stats. */
 dg_status dg_saturation_split(dg_handle* h, const void* U, double* T, int use_guess,
                               double* rho_v, double* rho_c, hipStream_t stream);
 
-/* nsteps SSP-RK steps in place on U.  dt: HOST array of 1 value (single mesh)
- * or nmembers values (batch). */
+/* nsteps steps of the SSP Runge-Kutta scheme of Section 3.3 (SSPRK(4,3),
+ * or SSPRK(3,3) by dg_params.rk) in place on U, each stage the right-hand
+ * side of dg_rhs (split, volume, faces, sources, diagonal mass) followed by
+ * the Shu-Osher update; with the sponge on, Section 3.6's relaxation closes
+ * every step.  U: caller-owned device array in the state layout.  dt: HOST
+ * array of 1 value (single mesh) or nmembers values (batch), each positive
+ * and finite, otherwise DG_EINVAL.  Uses the handle's stage buffers. */
 dg_status dg_rk_step(dg_handle* h, void* U, const double* dt, int nsteps, hipStream_t stream);
 
-/* Vector-Jacobian product of dg_rhs: U_bar = (d rhs / d U)^T dUdt_bar, with the
- * implicit-function derivative of the split.  Arrays in the state layout and
- * precision; U_bar is overwritten. */
+/* Vector-Jacobian product of dg_rhs: U_bar = (d rhs / d U)^T dUdt_bar, the
+ * transpose of the linearised Section 3.2 operator, with the derivative of
+ * the Section 2.2 split taken by the implicit-function theorem on its
+ * active branch.  Arrays in the state layout and precision, device,
+ * caller-owned; U_bar is overwritten and must not alias U or dUdt_bar
+ * (DG_EINVAL).  Lobatto basis without diffusion only (DG_EUNSUPPORTED). */
 dg_status dg_rhs_vjp(dg_handle* h, const void* U, const void* dUdt_bar, void* U_bar,
                      hipStream_t stream);
 
-/* Vector-Jacobian product of the split: U_bar = (d(T, rho_v, rho_c)/dU)^T
- * (T_bar, rho_v_bar, rho_c_bar).  The bar arrays are device doubles per node
- * (any may be NULL); U_bar is overwritten. */
+/* Vector-Jacobian product of the Section 2.2 split: U_bar =
+ * (d(T, rho_v, rho_c)/dU)^T (T_bar, rho_v_bar, rho_c_bar), by the
+ * implicit-function theorem.  The bar arrays are device doubles per node
+ * (any may be NULL); U_bar is overwritten and must not alias U. */
 dg_status dg_saturation_split_vjp(dg_handle* h, const void* U, const double* T_bar,
                                   const double* rho_v_bar, const double* rho_c_bar,
                                   void* U_bar, hipStream_t stream);
 
-/* Vector-Jacobian product of one RK step: U_n_bar = (d U_{n+1}/d U_n)^T
- * U_np1_bar.  The stages are recomputed from U_n.  dt as in dg_rk_step. */
+/* Vector-Jacobian product of one Section 3.3 RK step (with the sponge's
+ * transpose when it is on): U_n_bar = (d U_{n+1}/d U_n)^T U_np1_bar.  The
+ * stages are recomputed from U_n into the handle's buffers.  dt as in
+ * dg_rk_step; arrays as in dg_rhs_vjp (U_n_bar must not alias the others).
+ * Lobatto basis without diffusion only (DG_EUNSUPPORTED). */
 dg_status dg_rk_step_vjp(dg_handle* h, const void* U_n, const void* U_np1_bar, void* U_n_bar,
                          const double* dt, hipStream_t stream);
 
@@ -253,16 +273,26 @@ dg_status dg_destroy(dg_handle* h);
 dg_status dg_set_launch(dg_handle* h, int elems_per_block, int persist_per_cu);
 dg_status dg_get_launch(const dg_handle* h, int* elems_per_block, int* persist_per_cu);
 
+/* Order of the work items (3D handles; 2D items are always in element
+ * order): 0 (default) y-bands of rows with z inside a band, so the elements
+ * above and below an item were visited shortly before it; 1 plain element
+ * order; 2 y-bands twice as wide.  Results do not depend on it.  Not a hot
+ * call: synchronises.  DG_EINVAL for another value. */
+dg_status dg_set_item_order(dg_handle* h, int order);
+dg_status dg_get_item_order(const dg_handle* h, int* order);
+
 /* Autotuner: times nsteps RK steps of a copy of U (device) for every
  * candidate geometry (elements per block {max, max/2, max/4} x persistent
- * blocks per CU {0, 1, 2, 4}), keeps the fastest and reports it (any output
- * pointer may be NULL; best_ms is per step).  U is not modified. */
+ * blocks per CU {0, 1, 2, 4} x item order {0, 1, 2} in 3D), keeps the
+ * fastest and reports it (any output pointer may be NULL; best_ms is per
+ * step; the order is read back with dg_get_item_order).  U is not modified. */
 dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, int nsteps, int* best_epb,
                       int* best_persist, double* best_ms);
 
-/* dg_rk_step replayed from a captured hipGraph: the first call for a given
- * (U, nsteps, geometry) captures every kernel of the nsteps steps, later
- * calls replay it.  Kernel timing must be disabled. */
+/* dg_rk_step (Section 3.3) replayed from a captured hipGraph: the first call
+ * for a given (U, nsteps, launch geometry) captures every kernel of the
+ * nsteps steps, later calls replay it; dt is uploaded before each replay.
+ * Arguments as dg_rk_step.  Kernel timing must be disabled (DG_EINVAL). */
 dg_status dg_rk_step_graph(dg_handle* h, void* U, const double* dt, int nsteps, hipStream_t stream);
 
 /* Kernel timing (instrumentation).  While enabled, every kernel the library

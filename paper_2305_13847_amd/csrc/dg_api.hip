@@ -99,6 +99,7 @@ struct dg_handle {
   // launch geometry
   int epb = 1;                   // elements per block
   int persist = 0;               // persistent blocks per CU (0: one block per item)
+  int item_order = 0;            // order of the work items (build_items)
   int ncu = 256;
   long long items_cap = 0;       // device capacity of the item table
   // captured multi-step graph
@@ -343,7 +344,12 @@ static dg_status validate_mesh(const dg_mesh* m, int dim) {
 }
 
 // (Re)build the work-item table for `epb` elements per block.
-static void build_items(dg_handle* h, int epb) {
+// Item orders (3D members; a 2D member's items are always in element order):
+//   0: y-bands of `by` rows, z outside y inside a band (below);
+//   1: plain element order (x, then y, then z);
+//   2: y-bands twice as wide as in order 0.
+static void build_items(dg_handle* h, int epb, int order = -1) {
+  if (order < 0) order = h->item_order;
   h->items.clear();
   h->item_off.clear();
   for (int m = 0; m < h->nmembers; ++m) {
@@ -360,12 +366,12 @@ static void build_items(dg_handle* h, int epb) {
       it.c12 = c1 + (c2 << 16);
       h->items.push_back(it);
     }
-    if (h->dim == 3) {
+    if (h->dim == 3 && order != 1) {
       // Walk y-bands of `by` rows with z outside y inside a band, so the
       // elements above and below an item were visited at most ~64 items
       // earlier and are still in the XCD's L2 when their faces are read.
       const int per_row = (md.n[0] + epb - 1) / epb;
-      const int by = std::max(1, std::min(md.n[1], 64 / std::max(1, per_row)));
+      const int by = std::max(1, std::min(md.n[1], (order == 2 ? 128 : 64) / std::max(1, per_row)));
       auto key = [&](const Item& it) {
         const int c1 = it.c12 & 0xffff, c2 = it.c12 >> 16;
         return std::make_tuple(c1 / by, c2, c1 % by, it.c0);
@@ -376,6 +382,7 @@ static void build_items(dg_handle* h, int epb) {
   }
   h->item_off.push_back((int)h->items.size());
   h->epb = epb;
+  h->item_order = order;
 }
 
 static LaunchCfg launch_cfg(const dg_handle* h) {
@@ -1164,6 +1171,24 @@ extern "C" dg_status dg_set_launch(dg_handle* h, int epb, int persist) {
   return DG_OK;
 }
 
+extern "C" dg_status dg_set_item_order(dg_handle* h, int order) {
+  if (!h) return fail(DG_EINVAL, "null handle");
+  if (order < 0 || order > 2) return fail(DG_EINVAL, "item order must be 0, 1 or 2");
+  HIP_TRY(hipDeviceSynchronize());
+  if (order != h->item_order) {
+    build_items(h, h->epb, order);
+    dg_status st = upload_items(h);
+    if (st != DG_OK) return st;
+  }
+  return DG_OK;
+}
+
+extern "C" dg_status dg_get_item_order(const dg_handle* h, int* order) {
+  if (!h || !order) return fail(DG_EINVAL, "null pointer");
+  *order = h->item_order;
+  return DG_OK;
+}
+
 extern "C" dg_status dg_get_launch(const dg_handle* h, int* epb, int* persist) {
   if (!h) return fail(DG_EINVAL, "null handle");
   if (epb) *epb = h->epb;
@@ -1184,6 +1209,7 @@ extern "C" dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, 
   const int emax = elems_per_block(h->order, h->dim, h->prec == DG_FP64);
   const int cand_e[3] = {emax, emax / 2, emax / 4};
   const int cand_p[4] = {0, 1, 2, 4};
+  const int norders = h->dim == 3 ? 3 : 1;   // 2D items are always in element order
   void* W = h->stage_x[0];
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -1191,11 +1217,13 @@ extern "C" dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, 
   const bool timing = h->timing;
   h->timing = false;
   double best = 1e300;
-  int be = h->epb, bp = h->persist;
+  int be = h->epb, bp = h->persist, bo = h->item_order;
+  for (int io = 0; io < norders; ++io)
   for (int ie = 0; ie < 3; ++ie) {
     if (cand_e[ie] < 1 || (ie > 0 && cand_e[ie] == cand_e[ie - 1])) continue;
     for (int ip = 0; ip < 4; ++ip) {
-      st = dg_set_launch(h, cand_e[ie], cand_p[ip]);
+      st = dg_set_item_order(h, io);
+      if (st == DG_OK) st = dg_set_launch(h, cand_e[ie], cand_p[ip]);
       if (st != DG_OK) { h->timing = timing; return st; }
       HIP_TRY(hipMemcpy(W, U, h->state_bytes, hipMemcpyDeviceToDevice));
       int cur = 0;
@@ -1207,13 +1235,14 @@ extern "C" dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, 
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) { best = ms; be = cand_e[ie]; bp = cand_p[ip]; }
+      if (ms < best) { best = ms; be = cand_e[ie]; bp = cand_p[ip]; bo = io; }
     }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   h->timing = timing;
-  st = dg_set_launch(h, be, bp);
+  st = dg_set_item_order(h, bo);
+  if (st == DG_OK) st = dg_set_launch(h, be, bp);
   if (st != DG_OK) return st;
   if (best_epb) *best_epb = be;
   if (best_persist) *best_persist = bp;

@@ -122,7 +122,7 @@ struct Launch {
     });
   }
 
-  // artificial diffusion: alpha_K, vertex means (per member), tendency
+  // artificial diffusion: alpha_K, vertex means (all members), tendency
   static bool sip(const KArgs& a, LaunchCfg lc, int K, int D, int rain, int nmembers, const long long* nvert,
                   const void* U, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
@@ -132,9 +132,7 @@ struct Launch {
       const dim3 grid(grid_for_items(a.nitems));
       hipLaunchKernelGGL((sip_alpha_kernel<R, K_, D_, R_>), grid, dim3(lc.threads), 0, s, a,
                          (const R*)U);
-      for (int m = 0; m < nmembers; ++m)
-        hipLaunchKernelGGL((sip_vertex_kernel<D_>), dim3((unsigned)((nvert[m] + 127) / 128)), dim3(128), 0, s,
-                           a, m);
+      hipLaunchKernelGGL((sip_vertex_kernel<D_>), dim3((unsigned)((a.nvert + 127) / 128)), dim3(128), 0, s, a);
       hipLaunchKernelGGL((sip_kernel<R, K_, D_, R_>), grid, dim3(lc.threads), 0, s, a, (const R*)U);
     });
   }

@@ -6,7 +6,7 @@
 // each vertex.  Three kernels per right-hand side:
 //   1. sip_alpha_kernel: alpha_K of every element (two fields), an LDS
 //      reduction over the element's nodes;
-//   2. sip_vertex_kernel: the vertex means;
+//   2. sip_vertex_kernel: the vertex means (all members in one launch);
 //   3. sip_kernel: the tendency S = -M^{-1} A_h(U, .) at every node, written
 //      in the state layout; the stage kernels add it to the right-hand side.
 // With nodes at the Lobatto points, S at node i reads (d_j = 2/h_j, D the
@@ -81,14 +81,22 @@ sip_alpha_kernel(KArgs a, const R* __restrict__ U) {
   }
 }
 
-// one thread per vertex of member m: the mean of alpha_K over the elements
-// that share it (a periodic axis wraps, a walled one has n + 1 vertices)
+// one thread per vertex of every member (one launch for an ensemble): the
+// mean of alpha_K over the elements that share it (a periodic axis wraps, a
+// walled one has n + 1 vertices); the member is found by bisection over the
+// members' first vertices
 template <int D>
-__global__ void sip_vertex_kernel(KArgs a, int m) {
-  const MemberDesc& md = a.mem[m];
-  const long long nv = (long long)md.nvx[0] * md.nvx[1] * md.nvx[2];
-  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nv) return;
+__global__ void sip_vertex_kernel(KArgs a) {
+  const long long gi = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gi >= a.nvert) return;
+  int lo = 0, hi = a.nmembers - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a.mem[mid].voff <= gi) lo = mid;
+    else hi = mid - 1;
+  }
+  const MemberDesc& md = a.mem[lo];
+  const long long i = gi - md.voff;
   int v[3] = {(int)(i % md.nvx[0]), (int)((i / md.nvx[0]) % md.nvx[1]), (int)(i / ((long long)md.nvx[0] * md.nvx[1]))};
   double s0 = 0.0, s1 = 0.0;
   int cnt = 0;

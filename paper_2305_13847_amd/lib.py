@@ -58,7 +58,7 @@ EXPORTS = ["dg_default_params", "dg_create", "dg_create_batch", "dg_set_backgrou
            "dg_rhs_vjp", "dg_saturation_split_vjp", "dg_rk_step_vjp", "dg_reduce_mass", "dg_reduce_mass_member",
            "dg_get_stats", "dg_reset_stats", "dg_destroy", "dg_last_error", "dg_timing_enable",
            "dg_timing_read", "dg_set_launch", "dg_get_launch", "dg_autotune", "dg_rk_step_graph",
-           "dg_rhs_noalloc"]
+           "dg_rhs_noalloc", "dg_set_item_order", "dg_get_item_order"]
 DG_K_SPLIT, DG_K_STAGE, DG_K_ADJOINT, DG_K_OTHER = 0, 1, 2, 3
 
 _lib = None
@@ -98,6 +98,8 @@ def load(path: str = LIB_PATH):
     L.dg_timing_read.argtypes = [vp, ct.c_int, dp, ct.POINTER(ct.c_longlong)]
     L.dg_set_launch.argtypes = [vp, ct.c_int, ct.c_int]
     L.dg_get_launch.argtypes = [vp, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int)]
+    L.dg_set_item_order.argtypes = [vp, ct.c_int]
+    L.dg_get_item_order.argtypes = [vp, ct.POINTER(ct.c_int)]
     L.dg_autotune.argtypes = [vp, vp, dp, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), dp]
     L.dg_rk_step_graph.argtypes = [vp, vp, dp, ct.c_int, vp]
     L.dg_last_error.argtypes = []
@@ -258,6 +260,14 @@ class DG:
         _check(self.L.dg_get_launch(self.h, ct.byref(e), ct.byref(p)))
         return e.value, p.value
 
+    def set_item_order(self, order: int):
+        _check(self.L.dg_set_item_order(self.h, int(order)))
+
+    def get_item_order(self) -> int:
+        o = ct.c_int()
+        _check(self.L.dg_get_item_order(self.h, ct.byref(o)))
+        return o.value
+
     def autotune(self, U, dt, nsteps: int = 3, cache: Optional[str] = None, key: Optional[str] = None):
         """Pick elements per block and the persistent grid by timing; optional JSON cache."""
         import json
@@ -265,13 +275,15 @@ class DG:
             with open(cache) as f:
                 rec = json.load(f).get(key)
             if rec:
+                self.set_item_order(rec.get("item_order", 0))
                 self.set_launch(rec["elems_per_block"], rec["persist_per_cu"])
                 return rec
         dts = np.ascontiguousarray(np.atleast_1d(np.asarray(dt, dtype=np.float64)))
         e, p, ms = ct.c_int(), ct.c_int(), ct.c_double()
         _check(self.L.dg_autotune(self.h, self._state(U), dts.ctypes.data_as(ct.POINTER(ct.c_double)),
                                   int(nsteps), ct.byref(e), ct.byref(p), ct.byref(ms)))
-        rec = dict(elems_per_block=e.value, persist_per_cu=p.value, ms_per_step=ms.value)
+        rec = dict(elems_per_block=e.value, persist_per_cu=p.value, item_order=self.get_item_order(),
+                   ms_per_step=ms.value)
         if cache and key:
             data = {}
             if os.path.exists(cache):

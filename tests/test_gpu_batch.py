@@ -148,3 +148,22 @@ def test_persistent_grid_covers_every_item(basis, sip):
         outs.append((R, T, U.cpu().numpy()))
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("order3", [2, 3])
+def test_item_order_does_not_change_results(order3):
+    # the order of the work items (y-bands, plain, wide bands) changes only
+    # which elements run together, never the arithmetic
+    lib = _lib()
+    c = synth.warm_rain_3d(n=(6, 9, 4), order=order3, seed=19)
+    outs = []
+    for order in (0, 1, 2):
+        dg = lib.for_case(c, precision=1)
+        dg.set_item_order(order)
+        assert dg.get_item_order() == order
+        U = torch.tensor(c.U, dtype=torch.float32, device="cuda")
+        dg.rk_step(U, c.dt, 2)
+        outs.append(U.cpu().numpy())
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+    with pytest.raises(lib.DGError):
+        dg.set_item_order(3)
