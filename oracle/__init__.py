@@ -45,6 +45,12 @@ class OraMesh(ct.Structure):
 BASES = {"lobatto": 0, "gauss": 1}
 
 
+class OraTriMesh(ct.Structure):
+    _fields_ = [("ne", ct.c_int), ("xy", ct.POINTER(ct.c_double)), ("nb", ct.POINTER(ct.c_int)),
+                ("nbf", ct.POINTER(ct.c_int)), ("order", ct.c_int), ("z0", ct.c_double),
+                ("dz", ct.c_double), ("nz", ct.c_int)]
+
+
 _lib = None
 
 
@@ -91,6 +97,22 @@ def lib():
         L.ora_face.argtypes = [ct.c_void_p, dp, ct.c_int, dp, ct.c_int, ct.c_int, dp]
         L.ora_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_long), ct.POINTER(ct.c_int),
                                 ct.POINTER(ct.c_int)]
+        ip = ct.POINTER(ct.c_int)
+        L.ora_tri_rule.argtypes = [ct.c_int, dp, dp]
+        L.ora_tri_basis.argtypes = [ct.c_int, dp, ct.c_int, dp, dp, dp]
+        L.ora_tri_create.argtypes = [ct.POINTER(OraTriMesh), ct.POINTER(OraParams), ct.c_int, dp, dp, dp, dp]
+        L.ora_tri_create.restype = ct.c_void_p
+        L.ora_tri_destroy.argtypes = [ct.c_void_p]
+        L.ora_tri_points.argtypes = [ct.c_void_p, dp]
+        L.ora_tri_project.argtypes = [ct.c_void_p, dp, ct.c_int, dp]
+        L.ora_tri_eval.argtypes = [ct.c_void_p, dp, ct.c_int, dp, ct.c_int, dp]
+        L.ora_tri_background.argtypes = [ct.c_void_p, ct.c_double, dp]
+        L.ora_tri_split.argtypes = [ct.c_void_p, dp, dp, dp]
+        L.ora_tri_rhs.argtypes = [ct.c_void_p, dp, dp, dp]
+        L.ora_tri_rk_step.argtypes = [ct.c_void_p, dp, ct.c_double, ct.c_int, ct.c_int, dp]
+        L.ora_tri_mass.argtypes = [ct.c_void_p, dp, dp]
+        L.ora_tri_face.argtypes = [ct.c_void_p, dp, dp, ct.c_double, dp, dp]
+        L.ora_tri_stats.argtypes = [ct.c_void_p, ct.POINTER(ct.c_long), ct.POINTER(ct.c_int), ip]
         _lib = L
     return _lib
 
@@ -286,3 +308,137 @@ def set_threads(n: int) -> None:
 
 def get_threads() -> int:
     return int(lib().ora_get_threads())
+
+
+# ----------------------------------------------------------------------------
+# triangles
+# ----------------------------------------------------------------------------
+def tri_rule(k: int):
+    """The unit-triangle volume rule: points (n, 2) as (r, s) and weights (n,)."""
+    n = (k + 1) * (k + 2)
+    rs, w = np.zeros((n, 2)), np.zeros(n)
+    if lib().ora_tri_rule(k, _p(rs), _p(w)) != n:
+        raise ValueError("order out of range")
+    return rs, w
+
+
+def tri_basis(k: int, rs: np.ndarray):
+    """Orthonormal basis and its reference gradient at points rs (n, 2):
+    arrays (n, np) of psi, d/dr, d/ds."""
+    rs = np.ascontiguousarray(rs, dtype=np.float64).reshape(-1, 2)
+    npk = (k + 1) * (k + 2) // 2
+    psi, dr, ds = (np.zeros((rs.shape[0], npk)) for _ in range(3))
+    if lib().ora_tri_basis(k, _p(rs), rs.shape[0], _p(psi), _p(dr), _p(ds)) != npk:
+        raise ValueError("order out of range")
+    return psi, dr, ds
+
+
+class TriOracle:
+    """One triangulation + background; coefficients C[v][e][m] in float64."""
+
+    def __init__(self, mesh, params: OraParams, nvars: int, bg: Dict[str, np.ndarray]):
+        self.mesh, self.P, self.nvars = mesh, params, nvars
+        self._xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
+        self._nb = np.ascontiguousarray(mesh.nb, dtype=np.int32)
+        self._nbf = np.ascontiguousarray(mesh.nbf, dtype=np.int32)
+        M = OraTriMesh()
+        M.ne = mesh.ne
+        M.xy = _p(self._xy)
+        M.nb = self._nb.ctypes.data_as(ct.POINTER(ct.c_int))
+        M.nbf = self._nbf.ctypes.data_as(ct.POINTER(ct.c_int))
+        M.order = mesh.order
+        M.z0 = float(mesh.lo[1])
+        M.dz = float(mesh.h[1])
+        M.nz = int(mesh.n[1])
+        self._bg = [np.ascontiguousarray(bg[k], dtype=np.float64) for k in ("rho_d", "rho_m", "rho_r", "E")]
+        self.h = lib().ora_tri_create(ct.byref(M), ct.byref(params), nvars, *[_p(a) for a in self._bg])
+        if not self.h:
+            raise ValueError("oracle rejected the triangulation/order/nvars")
+        self.k = mesh.order
+        self.np = (self.k + 1) * (self.k + 2) // 2
+        self.nq = (self.k + 1) * (self.k + 2)
+        self.shape = (nvars, mesh.ne, self.np)
+
+    @classmethod
+    def for_case(cls, case, **over):
+        P = default_params(g=case.g, rain=case.rain, vr_const=case.vr_const, **over)
+        return cls(case.mesh, P, case.nvars, case.bg)
+
+    def __del__(self):
+        if getattr(self, "h", None) and lib is not None:
+            try:
+                lib().ora_tri_destroy(self.h)
+            except Exception:
+                pass
+            self.h = None
+
+    def points(self) -> np.ndarray:
+        """Physical coordinates of the volume points, (ne, nq, 2)."""
+        out = np.zeros((self.mesh.ne, self.nq, 2))
+        lib().ora_tri_points(self.h, _p(out))
+        return out
+
+    def project(self, vals: np.ndarray) -> np.ndarray:
+        """Coefficients of fields given at the volume points, (nf, ne, nq) -> (nf, ne, np)."""
+        vals = np.ascontiguousarray(vals, dtype=np.float64)
+        nf = vals.shape[0]
+        C = np.zeros((nf, self.mesh.ne, self.np))
+        lib().ora_tri_project(self.h, _p(vals), nf, _p(C))
+        return C
+
+    def state(self, point_state) -> np.ndarray:
+        """Coefficients of a state given as a function of position."""
+        return self.project(point_state(self.points()))
+
+    def eval(self, C: np.ndarray, rs: np.ndarray) -> np.ndarray:
+        """Fields C (nf, ne, np) at reference points rs (n, 2): (nf, ne, n)."""
+        C = np.ascontiguousarray(C, dtype=np.float64)
+        rs = np.ascontiguousarray(rs, dtype=np.float64).reshape(-1, 2)
+        out = np.zeros((C.shape[0], self.mesh.ne, rs.shape[0]))
+        lib().ora_tri_eval(self.h, _p(C), C.shape[0], _p(rs), rs.shape[0], _p(out))
+        return out
+
+    def background(self, z: float) -> np.ndarray:
+        out = np.zeros(5)
+        lib().ora_tri_background(self.h, float(z), _p(out))
+        return out
+
+    def split(self, C: np.ndarray):
+        """Coefficients of the projected T and rho_v, and the count of failed splits."""
+        C = np.ascontiguousarray(C, dtype=np.float64)
+        Tc, Rc = np.zeros(self.shape[1:]), np.zeros(self.shape[1:])
+        bad = lib().ora_tri_split(self.h, _p(C), _p(Tc), _p(Rc))
+        return Tc, Rc, bad
+
+    def rhs(self, C: np.ndarray, with_flux: bool = False):
+        C = np.ascontiguousarray(C, dtype=np.float64)
+        dC = np.zeros_like(C)
+        f = ct.c_double()
+        lib().ora_tri_rhs(self.h, _p(C), _p(dC), ct.byref(f))
+        return (dC, f.value) if with_flux else dC
+
+    def rk(self, C: np.ndarray, dt: float, nsteps: int, scheme: int = 0):
+        C = np.array(C, dtype=np.float64, order="C", copy=True)
+        f = ct.c_double()
+        lib().ora_tri_rk_step(self.h, _p(C), dt, nsteps, scheme, ct.byref(f))
+        return C, f.value
+
+    def mass(self, C: np.ndarray) -> np.ndarray:
+        C = np.ascontiguousarray(C, dtype=np.float64)
+        out = np.zeros(3)
+        lib().ora_tri_mass(self.h, _p(C), _p(out))
+        return out
+
+    def face(self, Um: np.ndarray, Up: np.ndarray, z: float, n) -> np.ndarray:
+        """Lax-Friedrichs flux along the unit normal n between two states at height z."""
+        Um = np.ascontiguousarray(Um, dtype=np.float64)
+        Up = np.ascontiguousarray(Up, dtype=np.float64)
+        nn = np.ascontiguousarray(n, dtype=np.float64)
+        Fs = np.zeros(self.nvars)
+        lib().ora_tri_face(self.h, _p(Um), _p(Up), float(z), _p(nn), _p(Fs))
+        return Fs
+
+    def stats(self):
+        it, mx, bad = ct.c_long(), ct.c_int(), ct.c_int()
+        lib().ora_tri_stats(self.h, ct.byref(it), ct.byref(mx), ct.byref(bad))
+        return dict(iters_total=it.value, max_iters=mx.value, bad=bad.value)

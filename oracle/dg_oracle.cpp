@@ -29,6 +29,11 @@
 //     see the traces of these projections.  States cross the interface as
 //     values at the Gauss points and are projected onto the Legendre basis on
 //     entry (and evaluated there on exit).
+// And on conforming triangulations of the vertical plane (Section 3.1, the
+// P^k space): the orthonormal Dubiner basis with its diagonal mass, the
+// Duffy-mapped product Gauss-Legendre rule of the footnote in Section 3.4,
+// faces gathered through a neighbour table; states cross the interface as
+// coefficients.
 //
 // The scalar type is a template parameter: `double` gives the reference
 // values, `Dual` (value + one tangent) gives exact directional derivatives of
@@ -1135,42 +1140,48 @@ template <class R> void any_sponge(Ctx& c, R* U) {
 }
 
 // SSP Runge-Kutta step in Shu-Osher form (Section 3.3 remark): SSPRK(4,3) of
-// Kraaijevanger, or the three-stage SSPRK(3,3); the sponge, when on, closes
-// the step.
-template <class R> void rk_step(Ctx& c, R* U, double dt, int scheme, double* outflow) {
-  const long N = (long)c.ne * c.np * c.nvars;
+// Kraaijevanger, or the three-stage SSPRK(3,3), on N unknowns U with the
+// right-hand side any_rhs(u, L, &wall_rain_flux).
+template <class R, class Rhs> void ssprk(long N, R* U, double dt, int scheme, Rhs&& any_rhs,
+                                         double* outflow) {
   std::vector<R> u0(U, U + N), us(N), L(N);
   double fl = 0.0, f = 0.0;
   if (scheme == 0) {
     // u1 = u0 + dt/2 L(u0); u2 = u1 + dt/2 L(u1);
     // u3 = 2/3 u0 + 1/3 u2 + dt/6 L(u2); u4 = u3 + dt/2 L(u3)
-    any_rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(u0.data(), L.data(), &f); fl += f / 6.0;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = u0[i] + (0.5 * dt) * L[i];
-    any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(us.data(), L.data(), &f); fl += f / 6.0;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = us[i] + (0.5 * dt) * L[i];
-    any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(us.data(), L.data(), &f); fl += f / 6.0;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = (2.0 / 3.0) * u0[i] + (1.0 / 3.0) * us[i] + (dt / 6.0) * L[i];
-    any_rhs(c, us.data(), L.data(), &f); fl += f / 2.0;
+    any_rhs(us.data(), L.data(), &f); fl += f / 2.0;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) U[i] = us[i] + (0.5 * dt) * L[i];
   } else {
     // u1 = u0 + dt L(u0); u2 = 3/4 u0 + 1/4 u1 + dt/4 L(u1);
     // u3 = 1/3 u0 + 2/3 u2 + 2/3 dt L(u2)
-    any_rhs(c, u0.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(u0.data(), L.data(), &f); fl += f / 6.0;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = u0[i] + dt * L[i];
-    any_rhs(c, us.data(), L.data(), &f); fl += f / 6.0;
+    any_rhs(us.data(), L.data(), &f); fl += f / 6.0;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) us[i] = 0.75 * u0[i] + 0.25 * us[i] + (0.25 * dt) * L[i];
-    any_rhs(c, us.data(), L.data(), &f); fl += f * (2.0 / 3.0);
+    any_rhs(us.data(), L.data(), &f); fl += f * (2.0 / 3.0);
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < N; ++i) U[i] = (1.0 / 3.0) * u0[i] + (2.0 / 3.0) * us[i] + ((2.0 / 3.0) * dt) * L[i];
   }
-  any_sponge(c, U);
   if (outflow) *outflow = fl * dt;
+}
+
+// The step of the box meshes; the sponge, when on, closes the step.
+template <class R> void rk_step(Ctx& c, R* U, double dt, int scheme, double* outflow) {
+  ssprk((long)c.ne * c.np * c.nvars, U, dt, scheme,
+        [&](const R* u, R* L, double* f) { any_rhs(c, u, L, f); }, outflow);
+  any_sponge(c, U);
 }
 
 }  // namespace
@@ -1492,6 +1503,577 @@ int ora_project(void* h, const double* U, double* C) {
 void ora_stats(void* h, long* iters_total, int* max_iters, int* bad) {
   Ctx* c = (Ctx*)h;
   *iters_total = c->iters_total; *max_iters = c->max_iters; *bad = c->bad;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Triangles (Section 3.1: the space P^k on a simplicial mesh)
+// ===========================================================================
+// A conforming triangulation in the vertical (x, z) plane, every element an
+// affine image x = V0 + A (r, s) of the unit triangle {r, s >= 0, r + s <= 1}
+// with counter-clockwise vertices V0, V1, V2, so det A > 0.  Face f joins V_f
+// and V_{f+1 mod 3}; the mesh supplies, per face, the neighbouring element
+// and its face (periodic pairs included), or -1 for a slip wall.  Two
+// counter-clockwise triangles run along their shared edge in opposite
+// directions.
+//
+//  * basis: the orthonormal Dubiner basis, the Legendre-Jacobi products of the
+//    collapsed coordinates, so the element mass matrix is det A times the
+//    identity (Section 3.1; diagonal mass);
+//  * volume rule: the footnote of Section 3.4, a product of Gauss-Legendre
+//    rules, k+1 points across and k+2 points up, carried onto the triangle by
+//    the Duffy map (exact for total degree 2k+1, as the k+1 point rule on an
+//    interval);
+//  * faces: the (k+1)-point Gauss-Legendre rule on every edge;
+//  * the split runs at the volume points; T and rho_v are L2-projected onto P^k
+//    and the fluxes and sources are assembled with the projected fields at
+//    every quadrature point (Section 3.4);
+//  * the background depends on height only.  It is given, like that of the box
+//    meshes with the Gauss basis, at the Gauss heights of n_z uniform layers;
+//    its pressure is the equation of state of its split there.  An element
+//    belongs to the layer that holds its centroid, and at every point of the
+//    element (volume and face points alike) each background field is the
+//    degree-k interpolant of that layer (so a triangulation whose rows are the
+//    layers sees a P^k background on every element).
+// Coefficients are stored C[v][e][m], mode m running over p = 0..k and, for
+// each p, q = 0..k-p.
+namespace {
+
+// Jacobi polynomial P_n^{(al,be)}(x), three-term recurrence
+template <class R> R jacobi(int n, double al, double be, R x) {
+  if (n == 0) return R(1.0);
+  R p0 = R(1.0);
+  R p1 = 0.5 * ((al - be) + (al + be + 2.0) * x);
+  for (int m = 2; m <= n; ++m) {
+    const double c = 2.0 * m + al + be;
+    const double a1 = 2.0 * m * (m + al + be) * (c - 2.0);
+    const double a2 = (c - 1.0) * (al * al - be * be);
+    const double a3 = (c - 1.0) * c * (c - 2.0);
+    const double a4 = 2.0 * (m + al - 1.0) * (m + be - 1.0) * c;
+    R p2 = ((a2 + a3 * x) * p1 - a4 * p0) / a1;
+    p0 = p1;
+    p1 = p2;
+  }
+  return p1;
+}
+
+inline int tri_np(int k) { return (k + 1) * (k + 2) / 2; }
+
+// Every basis function at (r, s):
+//   psi_pq = N_pq t^p P_p((2r - t)/t) P_q^{(2p+1,0)}(2s - 1),  t = 1 - s,
+// with t^p P_p((2r - t)/t) by the Legendre recurrence multiplied through by
+// t^(m+1) (no division by t) and N_pq^2 = 2 (2p+1) (p+q+1), the inverse of
+// the squared norm on the unit triangle.
+template <class R> void tri_basis(int k, R r, R s, R* psi) {
+  R t = 1.0 - s, X = 2.0 * r - t;
+  R L[16];
+  L[0] = R(1.0);
+  if (k >= 1) L[1] = X;
+  for (int m = 1; m < k; ++m) L[m + 1] = ((2.0 * m + 1.0) * X * L[m] - (double)m * t * t * L[m - 1]) / (m + 1.0);
+  int i = 0;
+  for (int p = 0; p <= k; ++p)
+    for (int q = 0; p + q <= k; ++q)
+      psi[i++] = std::sqrt(2.0 * (2 * p + 1) * (p + q + 1)) * L[p] * jacobi(q, 2.0 * p + 1.0, 0.0, 2.0 * s - 1.0);
+}
+
+// values and reference gradients (d/dr, d/ds), the derivatives by forward mode
+void tri_basis_grad(int k, double r, double s, double* psi, double* dr, double* ds) {
+  Dual a[136], b[136];
+  tri_basis(k, Dual(r, 1.0), Dual(s, 0.0), a);
+  tri_basis(k, Dual(r, 0.0), Dual(s, 1.0), b);
+  for (int m = 0; m < tri_np(k); ++m) {
+    psi[m] = a[m].v;
+    if (dr) dr[m] = a[m].d;
+    if (ds) ds[m] = b[m].d;
+  }
+}
+
+// The Duffy-mapped product rule: a in [-1, 1] across (k+1 Gauss points), b in
+// [-1, 1] up (k+2 points); s = (1 + b)/2, r = (1 + a)(1 - s)/2 and
+// dr ds = (1 - s)/4 da db.  Point q = j (k+1) + i for a_i, b_j.
+struct TriRule {
+  std::vector<double> r, s, w;
+};
+
+TriRule tri_volume_rule(int k) {
+  Gauss ga = make_gauss(k), gb = make_gauss(k + 1);
+  TriRule R;
+  for (int j = 0; j < k + 2; ++j)
+    for (int i = 0; i < k + 1; ++i) {
+      const double s = 0.5 * (1.0 + gb.x[j]);
+      R.s.push_back(s);
+      R.r.push_back(0.5 * (1.0 + ga.x[i]) * (1.0 - s));
+      R.w.push_back(ga.w[i] * gb.w[j] * (1.0 - s) / 4.0);
+    }
+  return R;
+}
+
+const double kRefV[3][2] = {{0.0, 0.0}, {1.0, 0.0}, {0.0, 1.0}};
+
+struct TriCtx {
+  Ctx base;                  // parameters, dimension 2 and the variable count
+  int k, np, nq, nf, ne;
+  std::vector<double> xy;    // ne x 3 vertices x (x, z)
+  std::vector<int> nb, nbf;  // ne x 3
+  TriRule vol;
+  Gauss gf;                  // k+1 points: faces and background layers
+  std::vector<double> psi_q, dr_q, ds_q;   // [q*np + m]
+  std::vector<double> psi_f;               // [(f*nf + i)*np + m]
+  double z0, dz;
+  int nz;
+  std::vector<double> bgl[5];              // rho_d, rho_m, rho_r, E, p at the layer heights
+};
+
+struct TriGeom {
+  double V[3][2];
+  double det;
+  double G[2][2];        // A^{-T}: grad_x = G grad_(r,s)
+  double n[3][2], len[3];
+};
+
+TriGeom tri_geom(const TriCtx& c, int e) {
+  TriGeom g;
+  for (int v = 0; v < 3; ++v)
+    for (int a = 0; a < 2; ++a) g.V[v][a] = c.xy[(size_t)e * 6 + 2 * v + a];
+  const double a00 = g.V[1][0] - g.V[0][0], a01 = g.V[2][0] - g.V[0][0];
+  const double a10 = g.V[1][1] - g.V[0][1], a11 = g.V[2][1] - g.V[0][1];
+  g.det = a00 * a11 - a01 * a10;
+  // A^{-1} = [a11 -a01; -a10 a00] / det, and G = A^{-T}
+  g.G[0][0] = a11 / g.det;  g.G[0][1] = -a10 / g.det;
+  g.G[1][0] = -a01 / g.det; g.G[1][1] = a00 / g.det;
+  for (int f = 0; f < 3; ++f) {
+    const double dx = g.V[(f + 1) % 3][0] - g.V[f][0], dzz = g.V[(f + 1) % 3][1] - g.V[f][1];
+    g.len[f] = std::sqrt(dx * dx + dzz * dzz);
+    // outward normal of a counter-clockwise triangle: the edge turned clockwise
+    g.n[f][0] = dzz / g.len[f];
+    g.n[f][1] = -dx / g.len[f];
+  }
+  return g;
+}
+
+double tri_z(const TriGeom& g, double r, double s) {
+  return g.V[0][1] + (g.V[1][1] - g.V[0][1]) * r + (g.V[2][1] - g.V[0][1]) * s;
+}
+
+// the layer that holds height z
+int tri_layer_of(const TriCtx& c, double z) {
+  int l = (int)std::floor((z - c.z0) / c.dz);
+  return std::max(0, std::min(l, c.nz - 1));
+}
+
+// the layer of an element: that of its centroid
+int tri_layer(const TriCtx& c, const TriGeom& g) {
+  return tri_layer_of(c, (g.V[0][1] + g.V[1][1] + g.V[2][1]) / 3.0);
+}
+
+// background (rho_d, rho_m, rho_r, E, p) at height z: the Lagrange interpolant
+// through the Gauss heights of layer l
+void tri_bg(const TriCtx& c, int l, double z, double* out) {
+  const int p1 = c.k + 1;
+  const double xi = 2.0 * (z - c.z0 - l * c.dz) / c.dz - 1.0;
+  double ell[16];
+  for (int i = 0; i < p1; ++i) {
+    ell[i] = 1.0;
+    for (int j = 0; j < p1; ++j)
+      if (j != i) ell[i] *= (xi - c.gf.x[j]) / (c.gf.x[i] - c.gf.x[j]);
+  }
+  for (int f = 0; f < 5; ++f) {
+    double v = 0.0;
+    for (int i = 0; i < p1; ++i) v += ell[i] * c.bgl[f][(size_t)l * p1 + i];
+    out[f] = v;
+  }
+}
+
+template <class R> R tri_expand(const R* cm, const double* psi, int np) {
+  R v = R(0.0);
+  for (int m = 0; m < np; ++m) v += cm[m] * psi[m];
+  return v;
+}
+
+// the state U' of element e at a point with basis values psi
+template <class R> void tri_state_at(const TriCtx& c, const R* C, int e, const double* psi, R* Ut) {
+  const long N = (long)c.ne * c.np;
+  for (int v = 0; v < c.base.nvars; ++v) Ut[v] = tri_expand(C + (long)v * N + (long)e * c.np, psi, c.np);
+}
+
+// the split of the full state at a point (Section 2.2): T and rho_v
+template <class R> void tri_split_point(const TriCtx& c, const R* Ut, const double* b, R* T, R* rv,
+                                        SplitStats* st) {
+  const Ctx& x = c.base;
+  const OraParams& P = x.P;
+  R rd = b[0] + Ut[v_rd()];
+  R rm = b[1] + Ut[v_rm()];
+  R rr = P.rain ? R(b[2]) + Ut[v_rr(x)] : R(0.0);
+  R rho = rd + rm + rr;
+  R ke = R(0.0);
+  for (int i = 0; i < 2; ++i) {
+    R mi = Ut[v_m(x, i)];
+    ke += 0.5 * mi * (mi / rho);
+  }
+  R re = (b[3] + Ut[v_E(x)]) - ke;
+  int ok = 1, iters = 0;
+  split(P, rd, rm, rr, re, T, rv, &ok, &iters);
+  st->iters_total += iters;
+  st->max_iters = std::max(st->max_iters, iters);
+  if (!ok) st->bad++;
+}
+
+// Lax-Friedrichs flux along the unit normal n (Section 3.2):
+// {F}.n + Lambda/2 (U- - U+), Lambda the larger of |u.n| + |v_r n_z| + c_m
+template <class R> void tri_lf(const TriCtx& c, const Point<R>& a, const R* Ua, const Point<R>& b,
+                               const R* Ub, const double* n, R* Fs) {
+  const int nv = c.base.nvars;
+  R la = absr(a.u[0] * n[0] + a.u[1] * n[1]) + absr(a.vr * n[1]) + a.cm;
+  R lb = absr(b.u[0] * n[0] + b.u[1] * n[1]) + absr(b.vr * n[1]) + b.cm;
+  R L = max_minus(la, lb);
+  for (int v = 0; v < nv; ++v)
+    Fs[v] = 0.5 * ((a.F[0][v] + b.F[0][v]) * n[0] + (a.F[1][v] + b.F[1][v]) * n[1]) + 0.5 * L * (Ua[v] - Ub[v]);
+}
+
+// T_h and rho_v,h: the split at the volume points, L2-projected onto P^k
+// (orthonormal basis: c_m = sum_q w_q psi_m(q) f(q), det A cancels)
+template <class R> void tri_project_split(TriCtx& c, const R* C, R* Tc, R* Rvc) {
+  const int np = c.np, nq = c.nq, nv = c.base.nvars;
+  SplitStats tot;
+#pragma omp parallel
+  {
+    SplitStats st;
+    std::vector<R> Ut(nv), Tq(nq), Rq(nq);
+#pragma omp for schedule(static)
+    for (int e = 0; e < c.ne; ++e) {
+      TriGeom g = tri_geom(c, e);
+      for (int q = 0; q < nq; ++q) {
+        double b[5];
+        tri_bg(c, tri_layer(c, g), tri_z(g, c.vol.r[q], c.vol.s[q]), b);
+        tri_state_at(c, C, e, &c.psi_q[(size_t)q * np], Ut.data());
+        tri_split_point(c, Ut.data(), b, &Tq[q], &Rq[q], &st);
+      }
+      for (int m = 0; m < np; ++m) {
+        R a = R(0.0), r = R(0.0);
+        for (int q = 0; q < nq; ++q) {
+          a += (c.vol.w[q] * c.psi_q[(size_t)q * np + m]) * Tq[q];
+          r += (c.vol.w[q] * c.psi_q[(size_t)q * np + m]) * Rq[q];
+        }
+        Tc[(long)e * np + m] = a;
+        Rvc[(long)e * np + m] = r;
+      }
+    }
+#pragma omp critical
+    {
+      tot.iters_total += st.iters_total;
+      tot.max_iters = std::max(tot.max_iters, st.max_iters);
+      tot.bad += st.bad;
+    }
+  }
+  c.base.iters_total += tot.iters_total;
+  c.base.max_iters = std::max(c.base.max_iters, tot.max_iters);
+  c.base.bad += tot.bad;
+}
+
+// Everything the flux needs at a point of element e (geometry g) with basis
+// values psi: U', the projected T and rho_v, and the background at height z.
+template <class R> void tri_point(const TriCtx& c, const R* C, const R* Tc, const R* Rvc, int e,
+                                  const TriGeom& g, const double* psi, double z, R* Ut, Point<R>& q,
+                                  double* b) {
+  tri_state_at(c, C, e, psi, Ut);
+  R T = tri_expand(Tc + (long)e * c.np, psi, c.np);
+  R rv = tri_expand(Rvc + (long)e * c.np, psi, c.np);
+  tri_bg(c, tri_layer(c, g), z, b);
+  point_core(c.base, Ut, T, rv, b[0], b[1], c.base.P.rain ? b[2] : 0.0, b[3], b[4], q);
+}
+
+// dC/dt (Section 3.2 weak form; Section 3.3 diagonal mass; Section 3.4
+// reconstruction), element by element:
+//   det A dC_m/dt = det A sum_q w_q (F . grad psi_m + G psi_m)(x_q)
+//                   - sum_f |e_f| sum_i (w_i / 2) F_n(x_fi) psi_m(x_fi),
+// F_n the Lax-Friedrichs flux along the element's outward normal; the
+// neighbour's trace at x_fi is its face point k - i.
+template <class R> void tri_rhs(TriCtx& c, const R* C, R* dC, double* wall_rain_flux) {
+  const int np = c.np, nq = c.nq, nf = c.nf, nv = c.base.nvars, k = c.k;
+  const long N = (long)c.ne * np;
+  std::vector<R> Tc(N), Rvc(N);
+  tri_project_split(c, C, Tc.data(), Rvc.data());
+  std::vector<double> wflux(c.ne, 0.0);
+#pragma omp parallel
+  {
+    std::vector<R> Ut(nv), Un(nv), Ug(nv), Fs(nv), acc((size_t)nv * np);
+#pragma omp for schedule(static)
+    for (int e = 0; e < c.ne; ++e) {
+      TriGeom g = tri_geom(c, e);
+      std::fill(acc.begin(), acc.end(), R(0.0));
+      // volume: flux against the physical gradient, sources against psi
+      for (int q = 0; q < nq; ++q) {
+        const double* psi = &c.psi_q[(size_t)q * np];
+        Point<R> pt;
+        double b[5];
+        tri_point(c, C, Tc.data(), Rvc.data(), e, g, psi, tri_z(g, c.vol.r[q], c.vol.s[q]), Ut.data(), pt, b);
+        for (int m = 0; m < np; ++m) {
+          const double gr = c.dr_q[(size_t)q * np + m], gs = c.ds_q[(size_t)q * np + m];
+          const double gx = g.G[0][0] * gr + g.G[0][1] * gs;
+          const double gz = g.G[1][0] * gr + g.G[1][1] * gs;
+          for (int v = 0; v < nv; ++v)
+            acc[(size_t)v * np + m] += c.vol.w[q] * (pt.F[0][v] * gx + pt.F[1][v] * gz + pt.G[v] * psi[m]);
+        }
+      }
+      // faces
+      for (int f = 0; f < 3; ++f) {
+        const int e2 = c.nb[(size_t)e * 3 + f], f2 = c.nbf[(size_t)e * 3 + f];
+        for (int i = 0; i < nf; ++i) {
+          const double t = 0.5 * (1.0 + c.gf.x[i]);
+          const double r = kRefV[f][0] + t * (kRefV[(f + 1) % 3][0] - kRefV[f][0]);
+          const double s = kRefV[f][1] + t * (kRefV[(f + 1) % 3][1] - kRefV[f][1]);
+          const double z = tri_z(g, r, s);
+          const double* psi = &c.psi_f[((size_t)f * nf + i) * np];
+          Point<R> pm, pp;
+          double bm[5], bp[5];
+          tri_point(c, C, Tc.data(), Rvc.data(), e, g, psi, z, Ut.data(), pm, bm);
+          if (e2 < 0) {
+            // slip wall: m+ = m- - 2 (m-.n) n, every other component and the
+            // reconstructed T, rho_v copied
+            for (int v = 0; v < nv; ++v) Ug[v] = Ut[v];
+            R mn = Ut[v_m(c.base, 0)] * g.n[f][0] + Ut[v_m(c.base, 1)] * g.n[f][1];
+            for (int a = 0; a < 2; ++a) Ug[v_m(c.base, a)] = Ut[v_m(c.base, a)] - 2.0 * mn * g.n[f][a];
+            point_core(c.base, Ug.data(), pm.T, pm.rv, bm[0], bm[1], c.base.P.rain ? bm[2] : 0.0, bm[3], bm[4], pp);
+            tri_lf(c, pm, Ut.data(), pp, Ug.data(), g.n[f], Fs.data());
+            if (c.base.P.rain) wflux[e] += g.len[f] * 0.5 * c.gf.w[i] * val(Fs[v_rr(c.base)]);
+          } else {
+            // the neighbour's own trace at the same physical point
+            const double* psi2 = &c.psi_f[((size_t)f2 * nf + (k - i)) * np];
+            TriGeom g2 = tri_geom(c, e2);
+            const double t2 = 0.5 * (1.0 + c.gf.x[k - i]);
+            const double r2 = kRefV[f2][0] + t2 * (kRefV[(f2 + 1) % 3][0] - kRefV[f2][0]);
+            const double s2 = kRefV[f2][1] + t2 * (kRefV[(f2 + 1) % 3][1] - kRefV[f2][1]);
+            tri_point(c, C, Tc.data(), Rvc.data(), e2, g2, psi2, tri_z(g2, r2, s2), Un.data(), pp, bp);
+            tri_lf(c, pm, Ut.data(), pp, Un.data(), g.n[f], Fs.data());
+          }
+          const double wf = g.len[f] * 0.5 * c.gf.w[i] / g.det;
+          for (int m = 0; m < np; ++m)
+            for (int v = 0; v < nv; ++v) acc[(size_t)v * np + m] -= (wf * psi[m]) * Fs[v];
+        }
+      }
+      for (int v = 0; v < nv; ++v)
+        for (int m = 0; m < np; ++m) dC[(long)v * N + (long)e * np + m] = acc[(size_t)v * np + m];
+    }
+  }
+  if (wall_rain_flux) {
+    double s = 0.0;
+    for (int e = 0; e < c.ne; ++e) s += wflux[e];
+    *wall_rain_flux = s;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+struct OraTriMesh {
+  int ne;
+  const double* xy;   // ne x 3 x 2: counter-clockwise vertices (x, z)
+  const int* nb;      // ne x 3: element across face f (V_f to V_f+1), -1 = slip wall
+  const int* nbf;     // ne x 3: that element's face index
+  int order;
+  // background layers: n_z layers of height dz from z0
+  double z0, dz;
+  int nz;
+};
+
+// the unit-triangle volume rule: (r, s) pairs and weights, (k+1)(k+2) points
+int ora_tri_rule(int k, double* rs, double* w) {
+  if (k < 1 || k > 8) return -1;
+  TriRule R = tri_volume_rule(k);
+  for (size_t q = 0; q < R.w.size(); ++q) {
+    rs[2 * q] = R.r[q];
+    rs[2 * q + 1] = R.s[q];
+    w[q] = R.w[q];
+  }
+  return (int)R.w.size();
+}
+
+// every basis function and its reference gradient at n points (r, s):
+// psi[i*np + m], dr[i*np + m], ds[i*np + m]
+int ora_tri_basis(int k, const double* rs, int n, double* psi, double* dr, double* ds) {
+  if (k < 1 || k > 8) return -1;
+  const int np = tri_np(k);
+  for (int i = 0; i < n; ++i)
+    tri_basis_grad(k, rs[2 * i], rs[2 * i + 1], psi + (size_t)i * np, dr ? dr + (size_t)i * np : nullptr,
+                   ds ? ds + (size_t)i * np : nullptr);
+  return np;
+}
+
+// A triangulation, its tables and its background (rho_d, rho_m, rho_r, E at
+// the n_z (k+1) Gauss heights of the layers, lowest layer first).
+void* ora_tri_create(const OraTriMesh* M, const OraParams* P, int nvars, const double* rd,
+                     const double* rm, const double* rr, const double* E) {
+  if (M->order < 1 || M->order > 8 || M->ne < 1 || M->nz < 1 || !(M->dz > 0.0)) return nullptr;
+  if (nvars != (P->rain ? 6 : 5)) return nullptr;
+  if (P->sip_gamma > 0.0 || P->sponge_alpha > 0.0) return nullptr;   // not on triangles
+  TriCtx* c = new TriCtx();
+  c->base.P = *P;
+  c->base.d = 2;
+  c->base.nvars = nvars;
+  c->base.k = M->order;
+  c->k = M->order;
+  c->np = tri_np(c->k);
+  c->ne = M->ne;
+  c->base.ne = M->ne;
+  c->base.np = c->np;
+  c->xy.assign(M->xy, M->xy + (size_t)M->ne * 6);
+  c->nb.assign(M->nb, M->nb + (size_t)M->ne * 3);
+  c->nbf.assign(M->nbf, M->nbf + (size_t)M->ne * 3);
+  for (int e = 0; e < c->ne; ++e) {
+    if (!(tri_geom(*c, e).det > 0.0)) { delete c; return nullptr; }
+    for (int f = 0; f < 3; ++f) {
+      const int e2 = c->nb[(size_t)e * 3 + f], f2 = c->nbf[(size_t)e * 3 + f];
+      if (e2 >= c->ne || (e2 >= 0 && (f2 < 0 || f2 > 2 || c->nb[(size_t)e2 * 3 + f2] != e))) { delete c; return nullptr; }
+    }
+  }
+  c->vol = tri_volume_rule(c->k);
+  c->nq = (int)c->vol.w.size();
+  c->gf = make_gauss(c->k);
+  c->nf = c->k + 1;
+  c->psi_q.resize((size_t)c->nq * c->np);
+  c->dr_q.resize((size_t)c->nq * c->np);
+  c->ds_q.resize((size_t)c->nq * c->np);
+  for (int q = 0; q < c->nq; ++q)
+    tri_basis_grad(c->k, c->vol.r[q], c->vol.s[q], &c->psi_q[(size_t)q * c->np], &c->dr_q[(size_t)q * c->np],
+                   &c->ds_q[(size_t)q * c->np]);
+  c->psi_f.resize((size_t)3 * c->nf * c->np);
+  for (int f = 0; f < 3; ++f)
+    for (int i = 0; i < c->nf; ++i) {
+      const double t = 0.5 * (1.0 + c->gf.x[i]);
+      const double r = kRefV[f][0] + t * (kRefV[(f + 1) % 3][0] - kRefV[f][0]);
+      const double s = kRefV[f][1] + t * (kRefV[(f + 1) % 3][1] - kRefV[f][1]);
+      tri_basis_grad(c->k, r, s, &c->psi_f[((size_t)f * c->nf + i) * c->np], nullptr, nullptr);
+    }
+  c->z0 = M->z0; c->dz = M->dz; c->nz = M->nz;
+  const int nzq = M->nz * (c->k + 1);
+  c->bgl[0].assign(rd, rd + nzq);
+  c->bgl[1].assign(rm, rm + nzq);
+  c->bgl[2].assign(nzq, 0.0);
+  if (P->rain) c->bgl[2].assign(rr, rr + nzq);
+  c->bgl[3].assign(E, E + nzq);
+  c->bgl[4].assign(nzq, 0.0);
+  for (int iz = 0; iz < nzq; ++iz) {
+    SplitOut s = split_double(*P, rd[iz], rm[iz], c->bgl[2][iz], E[iz]);
+    c->bgl[4][iz] = (rd[iz] * P->Rd + s.rv * P->Rv) * s.T;
+  }
+  return c;
+}
+
+void ora_tri_destroy(void* h) { delete (TriCtx*)h; }
+
+// physical coordinates of the volume points, xz[(e*nq + q)*2 + a]
+void ora_tri_points(void* h, double* xz) {
+  TriCtx* c = (TriCtx*)h;
+  for (int e = 0; e < c->ne; ++e) {
+    TriGeom g = tri_geom(*c, e);
+    for (int q = 0; q < c->nq; ++q)
+      for (int a = 0; a < 2; ++a)
+        xz[((size_t)e * c->nq + q) * 2 + a] = g.V[0][a] + (g.V[1][a] - g.V[0][a]) * c->vol.r[q]
+                                              + (g.V[2][a] - g.V[0][a]) * c->vol.s[q];
+  }
+}
+
+// L2 projection onto P^k of nfields fields given at the volume points:
+// vals[(f*ne + e)*nq + q] -> C[(f*ne + e)*np + m]
+void ora_tri_project(void* h, const double* vals, int nfields, double* C) {
+  TriCtx* c = (TriCtx*)h;
+  for (long b = 0; b < (long)nfields * c->ne; ++b)
+    for (int m = 0; m < c->np; ++m) {
+      double s = 0.0;
+      for (int q = 0; q < c->nq; ++q) s += c->vol.w[q] * c->psi_q[(size_t)q * c->np + m] * vals[b * c->nq + q];
+      C[b * c->np + m] = s;
+    }
+}
+
+// nfields fields C evaluated at n reference points of every element:
+// out[(f*ne + e)*n + i]
+void ora_tri_eval(void* h, const double* C, int nfields, const double* rs, int n, double* out) {
+  TriCtx* c = (TriCtx*)h;
+  std::vector<double> psi((size_t)n * c->np);
+  for (int i = 0; i < n; ++i) tri_basis_grad(c->k, rs[2 * i], rs[2 * i + 1], &psi[(size_t)i * c->np], nullptr, nullptr);
+  for (long b = 0; b < (long)nfields * c->ne; ++b)
+    for (int i = 0; i < n; ++i) out[b * n + i] = tri_expand(C + b * c->np, &psi[(size_t)i * c->np], c->np);
+}
+
+// background (rho_d, rho_m, rho_r, E, p) at height z (the layer that holds z)
+void ora_tri_background(void* h, double z, double* out5) {
+  TriCtx* c = (TriCtx*)h;
+  tri_bg(*c, tri_layer_of(*c, z), z, out5);
+}
+
+// T_h and rho_v,h coefficients of a state (Section 3.4 reconstruction)
+int ora_tri_split(void* h, const double* C, double* Tc, double* Rvc) {
+  TriCtx* c = (TriCtx*)h;
+  int bad = c->base.bad;
+  tri_project_split(*c, C, Tc, Rvc);
+  return c->base.bad - bad;
+}
+
+int ora_tri_rhs(void* h, const double* C, double* dC, double* wall_rain_flux) {
+  TriCtx* c = (TriCtx*)h;
+  int bad = c->base.bad;
+  tri_rhs(*c, C, dC, wall_rain_flux);
+  return c->base.bad - bad;
+}
+
+// nsteps steps of size dt in place; outflow as for the box meshes
+int ora_tri_rk_step(void* h, double* C, double dt, int nsteps, int scheme, double* outflow) {
+  TriCtx* c = (TriCtx*)h;
+  int bad = c->base.bad;
+  double acc = 0.0;
+  for (int s = 0; s < nsteps; ++s) {
+    double f = 0.0;
+    ssprk((long)c->ne * c->np * c->base.nvars, C, dt, scheme,
+          [&](const double* u, double* L, double* fl) { tri_rhs(*c, u, L, fl); }, &f);
+    acc += f;
+  }
+  if (outflow) *outflow = acc;
+  return c->base.bad - bad;
+}
+
+// M_d = int rho_d', M_w = int (rho_m' + rho_r') and the wall rain flux
+void ora_tri_mass(void* h, const double* C, double* out3) {
+  TriCtx* c = (TriCtx*)h;
+  const long N = (long)c->ne * c->np;
+  double md = 0.0, mw = 0.0;
+  for (int e = 0; e < c->ne; ++e) {
+    const double det = tri_geom(*c, e).det;
+    for (int q = 0; q < c->nq; ++q) {
+      const double* psi = &c->psi_q[(size_t)q * c->np];
+      md += det * c->vol.w[q] * tri_expand(C + (long)e * c->np, psi, c->np);
+      mw += det * c->vol.w[q] * (tri_expand(C + N + (long)e * c->np, psi, c->np)
+                                 + (c->base.P.rain ? tri_expand(C + 2 * N + (long)e * c->np, psi, c->np) : 0.0));
+    }
+  }
+  out3[0] = md;
+  out3[1] = mw;
+  std::vector<double> dC(N * c->base.nvars);
+  double f = 0.0;
+  tri_rhs(*c, C, dC.data(), &f);
+  out3[2] = f;
+}
+
+// Lax-Friedrichs flux along the unit normal n between the states Um and Up,
+// both split at height z
+void ora_tri_face(void* h, const double* Um, const double* Up, double z, const double* n, double* Fs) {
+  TriCtx* c = (TriCtx*)h;
+  double b[5];
+  tri_bg(*c, tri_layer_of(*c, z), z, b);
+  Point<double> a, bb;
+  SplitStats st;
+  double T, rv;
+  tri_split_point(*c, Um, b, &T, &rv, &st);
+  point_core(c->base, Um, T, rv, b[0], b[1], c->base.P.rain ? b[2] : 0.0, b[3], b[4], a);
+  tri_split_point(*c, Up, b, &T, &rv, &st);
+  point_core(c->base, Up, T, rv, b[0], b[1], c->base.P.rain ? b[2] : 0.0, b[3], b[4], bb);
+  tri_lf(*c, a, Um, bb, Up, n, Fs);
+}
+
+void ora_tri_stats(void* h, long* iters_total, int* max_iters, int* bad) {
+  TriCtx* c = (TriCtx*)h;
+  *iters_total = c->base.iters_total; *max_iters = c->base.max_iters; *bad = c->base.bad;
 }
 
 }  // extern "C"

@@ -217,8 +217,14 @@ def background(mesh: Mesh, Ts: float, ratio: Callable[[np.ndarray], np.ndarray],
     library consumes are returned (rho_d, rho_m, rho_r, E); the pressure is
     reconstructed by each solver from these.
     """
+    return background_at(node_heights(mesh), Ts, ratio, lapse, p0, g)
+
+
+def background_at(z, Ts: float, ratio: Callable[[np.ndarray], np.ndarray], lapse: float = 6.5e-3,
+                  p0: float = 1.0e5, g: float = 9.81) -> Dict[str, np.ndarray]:
+    """The profile of ``background`` at arbitrary heights z (any shape)."""
     from scipy.integrate import solve_ivp
-    z = node_heights(mesh)
+    z = np.asarray(z, dtype=np.float64)
 
     def parts(zz, p):
         T = Ts - lapse * zz
@@ -232,7 +238,7 @@ def background(mesh: Mesh, Ts: float, ratio: Callable[[np.ndarray], np.ndarray],
         _, rd, rm, _ = parts(zz, p)
         return -g * (rd + rm)
 
-    zs = np.unique(np.concatenate([[0.0], z]))
+    zs = np.unique(np.concatenate([[0.0], z.ravel()]))
     sol = solve_ivp(rhs, (0.0, float(zs[-1])), [p0], t_eval=zs, rtol=1e-12, atol=1e-9,
                     method="DOP853")
     p = np.interp(z, sol.t, sol.y[0])
@@ -528,3 +534,153 @@ def directions(mesh: Mesh, ndir=16, seed=6, centre=(10e3, 2e3)) -> np.ndarray:
             f += rng.standard_normal() * np.exp(-((X[0] - cx) ** 2 + (X[1] - cz) ** 2) / 1e6)
         out.append(f / np.sqrt(np.sum(f * f)))
     return np.stack(out)
+
+
+# ----------------------------------------------------------------------------
+# triangulations (the simplicial meshes of Section 3.1)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class TriMesh:
+    """Conforming triangulation of a box in the (x, z) plane.
+
+    Every cell of an n[0] x n[1] grid is cut along its rising diagonal into two
+    triangles.  ``xy[e, v]`` holds the counter-clockwise vertices of element e,
+    face f joins vertex f and vertex (f + 1) mod 3, ``nb[e, f]`` is the element
+    across face f (-1: slip wall) and ``nbf[e, f]`` that element's face; the
+    periodic pairs are in the tables.  Element 2 (j n[0] + i) + t is triangle t
+    of cell (i, j).  The background is described on the n[1] grid rows.
+    """
+    n: Sequence[int]
+    lo: Sequence[float]
+    hi: Sequence[float]
+    bc: Sequence[int]
+    order: int
+    xy: np.ndarray
+    nb: np.ndarray
+    nbf: np.ndarray
+
+    @property
+    def ne(self) -> int:
+        return int(self.xy.shape[0])
+
+    @property
+    def npe(self) -> int:
+        """Modes per element: the dimension of P^k in two variables."""
+        return (self.order + 1) * (self.order + 2) // 2
+
+    @property
+    def h(self) -> np.ndarray:
+        return (np.asarray(self.hi, float) - np.asarray(self.lo, float)) / np.asarray(self.n, float)
+
+    @property
+    def layers(self) -> Mesh:
+        """The grid rows as a box mesh: the background lives at its Gauss heights."""
+        return Mesh(2, list(self.n), list(self.lo), list(self.hi), list(self.bc), self.order, "gauss")
+
+    @property
+    def nzq(self) -> int:
+        return self.n[1] * (self.order + 1)
+
+
+def tri_mesh(n=(8, 4), lo=(0.0, 0.0), hi=(1.0, 1.0), bc=(PERIODIC, WALL), order=2, jitter=0.0,
+             seed=0) -> TriMesh:
+    """Structured triangulation with optional seeded vertex jitter.
+
+    ``jitter`` moves every vertex by up to that fraction of the cell size per
+    axis (uniform random); vertices on a slip wall move only along it, and
+    periodic images move together.
+    """
+    nx, nz = int(n[0]), int(n[1])
+    hx, hz = (hi[0] - lo[0]) / nx, (hi[1] - lo[1]) / nz
+    rng = np.random.default_rng(seed)
+    dxy = jitter * rng.uniform(-1.0, 1.0, size=(nx + 1, nz + 1, 2)) * np.array([hx, hz])
+    if bc[0] == PERIODIC:
+        dxy[nx] = dxy[0]
+    else:
+        dxy[0, :, 0] = dxy[nx, :, 0] = 0.0
+    if bc[1] == PERIODIC:
+        dxy[:, nz] = dxy[:, 0]
+    else:
+        dxy[:, 0, 1] = dxy[:, nz, 1] = 0.0
+    I, J = np.meshgrid(np.arange(nx + 1), np.arange(nz + 1), indexing="ij")
+    P = np.stack([lo[0] + I * hx, lo[1] + J * hz], axis=-1) + dxy        # (nx+1, nz+1, 2)
+    ne = 2 * nx * nz
+    xy = np.zeros((ne, 3, 2))
+    nb = np.full((ne, 3), -1, dtype=np.int32)
+    nbf = np.full((ne, 3), -1, dtype=np.int32)
+
+    def cell(i, j):
+        """First element of cell (i, j) after periodic wrapping, or -1 past a wall."""
+        if bc[0] == PERIODIC:
+            i %= nx
+        if bc[1] == PERIODIC:
+            j %= nz
+        if not (0 <= i < nx and 0 <= j < nz):
+            return -1
+        return 2 * (j * nx + i)
+
+    for j in range(nz):
+        for i in range(nx):
+            e = cell(i, j)
+            v00, v10, v11, v01 = P[i, j], P[i + 1, j], P[i + 1, j + 1], P[i, j + 1]
+            xy[e] = (v00, v10, v11)
+            xy[e + 1] = (v00, v11, v01)
+            # lower triangle: bottom edge, right edge, diagonal
+            for f, (c2, t2, f2) in enumerate([(cell(i, j - 1), 1, 1), (cell(i + 1, j), 1, 2), (e, 1, 0)]):
+                if c2 >= 0:
+                    nb[e, f], nbf[e, f] = c2 + t2, f2
+            # upper triangle: diagonal, top edge, left edge
+            for f, (c2, t2, f2) in enumerate([(e, 0, 2), (cell(i, j + 1), 0, 0), (cell(i - 1, j), 0, 1)]):
+                if c2 >= 0:
+                    nb[e + 1, f], nbf[e + 1, f] = c2 + t2, f2
+    return TriMesh([nx, nz], list(lo), list(hi), list(bc), order, xy, nb, nbf)
+
+
+@dataclasses.dataclass
+class TriCase:
+    """A workload on a triangulation: the state is a function of position.
+
+    ``point_state(xz)`` maps coordinates of shape (..., 2) to the perturbation
+    state (nvars, ...) there; each solver samples it at its own quadrature
+    points and projects onto its basis.  ``bg`` holds rho_d, rho_m, rho_r, E at
+    the Gauss heights of the grid rows (``mesh.layers``).
+    """
+    name: str
+    mesh: TriMesh
+    nvars: int
+    rain: int
+    g: float
+    vr_const: float
+    bg: Dict[str, np.ndarray]
+    point_state: Callable[[np.ndarray], np.ndarray]
+    dt: float
+    nsteps: int
+    seed: int
+
+
+def tri_bubble(n=(64, 32), order=3, seed=7, nsteps=100, amp=2.0, centre=(10e3, 2e3), radius=2e3,
+               ratio=1.3, Ts=300.0, top=10e3, jitter=0.0) -> TriCase:
+    """The 2D moist rising bubble of ``moist_bubble`` on a triangulation.
+
+    Domain 20 km x `top`, periodic in x, slip walls in z, gravity on, no rain
+    (the shape of the paper's bubble run on triangles, Section 4.2).
+    """
+    mesh = tri_mesh(n, (0.0, 0.0), (20e3, top), (PERIODIC, WALL), order, jitter, seed)
+    bgf = background(mesh.layers, Ts, lambda z: ratio + 0.0 * z)
+    bg = {k: bgf[k] for k in ("rho_d", "rho_m", "rho_r", "E")}
+
+    def point_state(xz):
+        xz = np.asarray(xz, dtype=np.float64)
+        X = [xz[..., 0], xz[..., 1]]
+        b = background_at(X[1], Ts, lambda z: ratio + 0.0 * z)
+        th = bubble(X, centre, radius, amp)
+        Tp = th * (b["p"] / C["pref"]) ** (C["Rd"] / C["cpd"])
+        E1 = partitioned_energy(b["rho_d"], b["rho_m"], b["rho_r"], b["T"] + Tp)
+        E0 = partitioned_energy(b["rho_d"], b["rho_m"], b["rho_r"], b["T"])
+        z = np.zeros_like(th)
+        return np.ascontiguousarray(np.stack([z, z, z, z, E1 - E0]))
+
+    h = float(np.min(mesh.h))
+    dt = float(0.2 * 0.5 * h / ((2 * order + 1) * (C_BOUND + 5.0)))
+    return TriCase("bubble-2d-p%d-%dx%dx2%s" % (order, n[0], n[1], "-jitter" if jitter else ""), mesh, 5, 0,
+                   C["g"], 0.0, bg, point_state, dt, nsteps, seed)

@@ -83,9 +83,13 @@ def moist_contact(mesh, t, u0=(20.0, 10.0), p=8e4, Tm=285.0, dT=4.0, cloud=3e-3)
     T varies smoothly, the vapour is at saturation, cloud water varies and the
     dry density closes the equation of state, so every field is advected.
     """
-    X = synth.node_coords(mesh)
-    L = np.asarray(mesh.hi) - np.asarray(mesh.lo)
-    s = [2 * np.pi * (X[a] - mesh.lo[a] - u0[a] * t) / L[a] for a in range(2)]
+    return moist_contact_at(synth.node_coords(mesh), mesh.lo, np.asarray(mesh.hi) - np.asarray(mesh.lo), t, u0,
+                            p, Tm, dT, cloud)
+
+
+def moist_contact_at(X, lo, L, t, u0=(20.0, 10.0), p=8e4, Tm=285.0, dT=4.0, cloud=3e-3):
+    """The moist contact at the points X = [x, z] of a periodic box lo + [0, L]."""
+    s = [2 * np.pi * (X[a] - lo[a] - u0[a] * t) / L[a] for a in range(2)]
     T = Tm + dT * np.sin(s[0]) * np.cos(s[1])
     rc = cloud * (1.2 + np.cos(s[0] + 2 * s[1]))
     rv = rho_vs_vec(T)
@@ -114,3 +118,23 @@ def node_weights(mesh):
         idx = (np.arange(p1 ** mesh.dim) // (p1 ** a)) % p1
         W *= w[idx]
     return W[None, :] * np.prod(mesh.h) / 2 ** mesh.dim * np.ones((mesh.ne, 1))
+
+
+def tri_conservative(rd, rv, rc, rr, T, u, rain=False):
+    """Conservative fields (rho_d, rho_m, [rho_r], m_x, m_z, E) from primitives."""
+    rm = rv + rc
+    rho = rd + rm + rr
+    m = [rho * ua for ua in u]
+    ke = 0.5 * sum(ma * ma for ma in m) / rho
+    E = (P0.cvd * rd + P0.cvv * rv + P0.cl * (rc + rr)) * (T - P0.Tref) \
+        + rv * (P0.Lref - P0.Rv * P0.Tref) + ke
+    return [rd, rm] + ([rr] if rain else []) + m + [E]
+
+
+def tri_l2(o, C):
+    """L2 norm of fields C (nf, ne, np) on the triangulation of o: the basis is
+    orthonormal on the unit triangle, so |f|^2 = sum_e det A_e sum_m c_m^2."""
+    xy = o.mesh.xy
+    det = (xy[:, 1, 0] - xy[:, 0, 0]) * (xy[:, 2, 1] - xy[:, 0, 1]) \
+        - (xy[:, 2, 0] - xy[:, 0, 0]) * (xy[:, 1, 1] - xy[:, 0, 1])
+    return np.sqrt(np.sum(det[None, :, None] * C * C, axis=(1, 2)))

@@ -34,13 +34,32 @@ MUTATIONS = [
     # the core right-hand side (Sections 2.3, 3.2, 3.3)
     ("gravity sign", "q.G[v_m(c, z)] = -rhop * P.g;", "q.G[v_m(c, z)] = rhop * P.g;",
      ["test_oracle_rhs.py"]),
-    ("jump sign", "0.5 * L * (Ua[v] - Ub[v]);", "0.5 * L * (Ub[v] - Ua[v]);", ["test_oracle_rhs.py"]),
+    ("jump sign", "b.F[j][v]) + 0.5 * L * (Ua[v] - Ub[v]);", "b.F[j][v]) + 0.5 * L * (Ub[v] - Ua[v]);",
+     ["test_oracle_rhs.py"]),
     ("wall not reflected", "Ug[v_m(c, j)] = -Ua[v_m(c, j)];", "Ug[v_m(c, j)] = Ua[v_m(c, j)];",
      ["test_oracle_rhs.py"]),
     ("v_r left out of the wave speed", "q.lam[j] = absr(q.u[j]) + absr(vz) + q.cm;",
      "q.lam[j] = absr(q.u[j]) + q.cm;", ["test_oracle_rhs.py"]),
     ("transposed volume matrix", "s += c.tab.Dhat[ij * p1 + a] *", "s += c.tab.Dhat[a * p1 + ij] *",
      ["test_oracle_rhs.py"]),
+    # triangles (Section 3.1 space, Section 3.4 rule, Section 3.2 flux)
+    ("Duffy weight without the collapse factor", "R.w.push_back(ga.w[i] * gb.w[j] * (1.0 - s) / 4.0);",
+     "R.w.push_back(ga.w[i] * gb.w[j] / 4.0);", ["test_oracle_tri.py"]),
+    ("triangle normal turned the wrong way", "g.n[f][0] = dzz / g.len[f];", "g.n[f][0] = -dzz / g.len[f];",
+     ["test_oracle_tri.py"]),
+    ("inverse Jacobian not transposed", "g.G[0][1] = -a10 / g.det;", "g.G[0][1] = -a01 / g.det;",
+     ["test_oracle_tri.py"]),
+    ("neighbour's face points not reversed", "&c.psi_f[((size_t)f2 * nf + (k - i)) * np]",
+     "&c.psi_f[((size_t)f2 * nf + i) * np]", ["test_oracle_tri.py"]),
+    ("triangle wall reflects all momentum",
+     "Ug[v_m(c.base, a)] = Ut[v_m(c.base, a)] - 2.0 * mn * g.n[f][a];",
+     "Ug[v_m(c.base, a)] = -Ut[v_m(c.base, a)];", ["test_oracle_tri.py"]),
+    ("triangle wave speed without v_r", "R lb = absr(b.u[0] * n[0] + b.u[1] * n[1]) + absr(b.vr * n[1]) + b.cm;",
+     "R lb = absr(b.u[0] * n[0] + b.u[1] * n[1]) + b.cm;", ["test_oracle_tri.py"]),
+    ("triangle jump sign", "b.F[1][v]) * n[1]) + 0.5 * L * (Ua[v] - Ub[v]);",
+     "b.F[1][v]) * n[1]) + 0.5 * L * (Ub[v] - Ua[v]);", ["test_oracle_tri.py"]),
+    ("triangle face weight doubled", "const double wf = g.len[f] * 0.5 * c.gf.w[i] / g.det;",
+     "const double wf = g.len[f] * c.gf.w[i] / g.det;", ["test_oracle_tri.py"]),
     ("RK weight", "us[i] = (2.0 / 3.0) * u0[i] + (1.0 / 3.0) * us[i] + (dt / 6.0) * L[i];",
      "us[i] = (2.0 / 3.0) * u0[i] + (1.0 / 3.0) * us[i] + (dt / 5.0) * L[i];",
      ["test_oracle_rhs.py", "test_oracle_convergence.py"]),
