@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 OUT = os.path.join(HERE, "libdgmoist.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["dg_api.hip", "dg_f64.hip", "dg_f32.hip"]
+SOURCES = ["dg_api.hip", "dg_f64.hip", "dg_f32.hip", "dg_tri_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          # no packed-FP32 instructions in generated code

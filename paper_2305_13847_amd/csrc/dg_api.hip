@@ -49,6 +49,31 @@ static dg_status fail(dg_status s, const char* fmt, ...) {
 
 extern "C" const char* dg_last_error(void) { return g_err.c_str(); }
 
+namespace dgm {
+// error reporting and the thermodynamic part of the kernel arguments, shared
+// with the triangle interface
+dg_status api_fail(dg_status s, const char* msg) {
+  g_err = msg;
+  return s;
+}
+
+void fill_thermo(KArgs& a, const dg_params* p) {
+  a.g = p->g; a.cvd = p->cvd; a.cvv = p->cvv; a.cl = p->cl; a.Rd = p->Rd; a.Rv = p->Rv;
+  a.Tref = p->Tref;
+  a.Lp = p->Lref - p->Rv * p->Tref;
+  const double aa = (p->cpv - p->cl) / p->Rv;
+  a.am1 = aa - 1.0;
+  a.b = (p->Lref - (p->cpv - p->cl) * p->Tref) / p->Rv;
+  a.inv_Tref = 1.0 / p->Tref;
+  a.C0 = p->eref / (p->Rv * p->Tref);
+  a.vr_const = p->vr_const;
+  a.vr_pref = std::pow(M_PI * p->rho_w * p->N0r, -0.125) * p->v0r * std::tgamma(4.5) / 6.0;
+  a.q_au = p->q_au;
+  a.rain = p->rain; a.vr_mode = p->vr_mode;
+  a.rtol = p->newton_rtol; a.maxit = p->newton_maxit;
+}
+}  // namespace dgm
+
 // ---------------------------------------------------------------------------
 // handle
 // ---------------------------------------------------------------------------
@@ -569,19 +594,7 @@ extern "C" dg_status dg_create_batch(const dg_mesh* meshes, int nmembers, int or
 
   // kernel argument block
   KArgs& a = h->ka;
-  a.g = p->g; a.cvd = p->cvd; a.cvv = p->cvv; a.cl = p->cl; a.Rd = p->Rd; a.Rv = p->Rv;
-  a.Tref = p->Tref;
-  a.Lp = p->Lref - p->Rv * p->Tref;
-  const double aa = (p->cpv - p->cl) / p->Rv;
-  a.am1 = aa - 1.0;
-  a.b = (p->Lref - (p->cpv - p->cl) * p->Tref) / p->Rv;
-  a.inv_Tref = 1.0 / p->Tref;
-  a.C0 = p->eref / (p->Rv * p->Tref);
-  a.vr_const = p->vr_const;
-  a.vr_pref = std::pow(M_PI * p->rho_w * p->N0r, -0.125) * p->v0r * std::tgamma(4.5) / 6.0;
-  a.q_au = p->q_au;
-  a.rain = p->rain; a.vr_mode = p->vr_mode;
-  a.rtol = p->newton_rtol; a.maxit = p->newton_maxit;
+  fill_thermo(a, p);
   a.basis = p->basis;
   double xnode[kMaxP1];
   if (p->basis == DG_BASIS_GAUSS) {

@@ -48,6 +48,11 @@ class dg_params(ct.Structure):
                 ("sip_gamma", ct.c_double), ("sip_sigma", ct.c_double)]
 
 
+class dg_tri_mesh(ct.Structure):
+    _fields_ = [("ne", ct.c_int), ("xy", ct.POINTER(ct.c_double)), ("nb", ct.POINTER(ct.c_int)),
+                ("nbf", ct.POINTER(ct.c_int)), ("z0", ct.c_double), ("dz", ct.c_double), ("nz", ct.c_int)]
+
+
 class dg_stats(ct.Structure):
     _fields_ = [("splits", ct.c_longlong), ("nonconverged", ct.c_longlong),
                 ("max_iters", ct.c_int), ("nonfinite", ct.c_int)]
@@ -58,7 +63,11 @@ EXPORTS = ["dg_default_params", "dg_create", "dg_create_batch", "dg_set_backgrou
            "dg_rhs_vjp", "dg_saturation_split_vjp", "dg_rk_step_vjp", "dg_reduce_mass", "dg_reduce_mass_member",
            "dg_get_stats", "dg_reset_stats", "dg_destroy", "dg_last_error", "dg_timing_enable",
            "dg_timing_read", "dg_set_launch", "dg_get_launch", "dg_autotune", "dg_rk_step_graph",
-           "dg_rhs_noalloc", "dg_set_item_order", "dg_get_item_order"]
+           "dg_rhs_noalloc", "dg_set_item_order", "dg_get_item_order",
+           # triangles (include/dg_tri.h)
+           "dg_tri_create", "dg_tri_set_background", "dg_tri_points", "dg_tri_state_size", "dg_tri_npoints",
+           "dg_tri_project", "dg_tri_split", "dg_tri_rhs", "dg_tri_rk_step", "dg_tri_get_stats",
+           "dg_tri_reset_stats", "dg_tri_timing_enable", "dg_tri_timing_read", "dg_tri_destroy"]
 DG_K_SPLIT, DG_K_STAGE, DG_K_ADJOINT, DG_K_OTHER = 0, 1, 2, 3
 
 _lib = None
@@ -102,10 +111,27 @@ def load(path: str = LIB_PATH):
     L.dg_get_item_order.argtypes = [vp, ct.POINTER(ct.c_int)]
     L.dg_autotune.argtypes = [vp, vp, dp, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), dp]
     L.dg_rk_step_graph.argtypes = [vp, vp, dp, ct.c_int, vp]
+    L.dg_tri_create.argtypes = [ct.POINTER(dg_tri_mesh), ct.c_int, ct.c_int, ct.POINTER(dg_params), ct.POINTER(vp)]
+    L.dg_tri_set_background.argtypes = [vp, dp, dp, dp, dp]
+    L.dg_tri_points.argtypes = [vp, dp]
+    L.dg_tri_state_size.argtypes = [vp]
+    L.dg_tri_state_size.restype = ct.c_longlong
+    L.dg_tri_npoints.argtypes = [vp]
+    L.dg_tri_npoints.restype = ct.c_longlong
+    L.dg_tri_project.argtypes = [vp, vp, ct.c_int, vp, vp]
+    L.dg_tri_split.argtypes = [vp, vp, vp, vp, vp]
+    L.dg_tri_rhs.argtypes = [vp, vp, vp, vp]
+    L.dg_tri_rk_step.argtypes = [vp, vp, ct.c_double, ct.c_int, vp]
+    L.dg_tri_get_stats.argtypes = [vp, ct.POINTER(dg_stats)]
+    L.dg_tri_reset_stats.argtypes = [vp]
+    L.dg_tri_timing_enable.argtypes = [vp, ct.c_int]
+    L.dg_tri_timing_read.argtypes = [vp, ct.c_int, dp, ct.POINTER(ct.c_longlong)]
+    L.dg_tri_destroy.argtypes = [vp]
     L.dg_last_error.argtypes = []
     L.dg_last_error.restype = ct.c_char_p
     for name in EXPORTS:
-        if name not in ("dg_default_params", "dg_state_size", "dg_last_error"):
+        if name not in ("dg_default_params", "dg_state_size", "dg_last_error", "dg_tri_state_size",
+                        "dg_tri_npoints"):
             getattr(L, name).restype = ct.c_int
     _lib = L
     return L
@@ -371,4 +397,137 @@ def for_ensemble(cases, precision=DG_FP32_BULK, **over) -> DG:
     dg = DG([c.mesh for c in cases], c0.mesh.order, c0.nvars, params_for_case(c0, precision, **over))
     for m, c in enumerate(cases):
         dg.set_background(m, c.bg["rho_d"], c.bg["rho_m"], c.bg["rho_r"], c.bg["E"])
+    return dg
+
+
+class DGTri:
+    """A triangulation handle (include/dg_tri.h): coefficients C[v][e][m]."""
+
+    def __init__(self, mesh, nvars: int, params: dg_params):
+        import torch
+        self.L = load()
+        self.mesh, self.nvars, self.params = mesh, nvars, params
+        self.order = int(mesh.order)
+        self.dtype = torch.float64 if params.precision == DG_FP64 else torch.float32
+        self._xy = np.ascontiguousarray(mesh.xy, dtype=np.float64)
+        self._nb = np.ascontiguousarray(mesh.nb, dtype=np.int32)
+        self._nbf = np.ascontiguousarray(mesh.nbf, dtype=np.int32)
+        m = dg_tri_mesh()
+        m.ne = int(mesh.ne)
+        m.xy = self._xy.ctypes.data_as(ct.POINTER(ct.c_double))
+        m.nb = self._nb.ctypes.data_as(ct.POINTER(ct.c_int))
+        m.nbf = self._nbf.ctypes.data_as(ct.POINTER(ct.c_int))
+        m.z0 = float(mesh.lo[1])
+        m.dz = float(mesh.h[1])
+        m.nz = int(mesh.n[1])
+        h = ct.c_void_p()
+        _check(self.L.dg_tri_create(ct.byref(m), self.order, nvars, ct.byref(params), ct.byref(h)))
+        self.h = h
+        self.size = int(self.L.dg_tri_state_size(h))
+        self.npoints = int(self.L.dg_tri_npoints(h))
+        self.np = (self.order + 1) * (self.order + 2) // 2
+        self.nq = (self.order + 1) * (self.order + 2)
+        self.ne = int(mesh.ne)
+
+    @property
+    def shape(self):
+        return (self.nvars, self.ne, self.np)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.dg_tri_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _coef(self, t, nfields, name="C"):
+        import torch
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError("%s must be a CUDA tensor" % name)
+        if t.dtype != self.dtype or not t.is_contiguous() or t.numel() != nfields * self.ne * self.np:
+            raise ValueError("%s must be a contiguous %s tensor with %d values" % (name, self.dtype,
+                                                                                  nfields * self.ne * self.np))
+        return ct.c_void_p(t.data_ptr())
+
+    def set_background(self, rho_d, rho_m, rho_r, E):
+        arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho_d, rho_m, rho_r, E)]
+        n = int(self.mesh.n[1]) * (self.order + 1)
+        if any(a.size != n for a in arrs):
+            raise ValueError("background arrays need %d values" % n)
+        self._bg = arrs
+        dp = ct.POINTER(ct.c_double)
+        _check(self.L.dg_tri_set_background(self.h, *[a.ctypes.data_as(dp) for a in arrs]))
+
+    def points(self) -> np.ndarray:
+        """Physical coordinates of the volume points, (ne, nq, 2)."""
+        out = np.zeros((self.ne, self.nq, 2))
+        _check(self.L.dg_tri_points(self.h, out.ctypes.data_as(ct.POINTER(ct.c_double))))
+        return out
+
+    def project(self, vals, stream=None):
+        """Coefficients (nf, ne, np) of fields given at the volume points (nf, ne, nq), float64 on the GPU."""
+        import torch
+        if not isinstance(vals, torch.Tensor) or not vals.is_cuda or vals.dtype != torch.float64 \
+                or not vals.is_contiguous() or vals.numel() % (self.ne * self.nq) != 0:
+            raise ValueError("vals must be a contiguous CUDA float64 tensor of nf x ne x nq values")
+        nf = vals.numel() // (self.ne * self.nq)
+        out = torch.empty((nf, self.ne, self.np), dtype=self.dtype, device=vals.device)
+        _check(self.L.dg_tri_project(self.h, ct.c_void_p(vals.data_ptr()), nf, ct.c_void_p(out.data_ptr()),
+                                     ct.c_void_p(_stream(stream))))
+        return out
+
+    def state(self, point_state, device="cuda"):
+        """Coefficients of a state given as a function of position (projected on the GPU)."""
+        import torch
+        vals = torch.from_numpy(np.ascontiguousarray(point_state(self.points()), dtype=np.float64)).to(device)
+        return self.project(vals)
+
+    def split(self, C, stream=None):
+        """Coefficients (ne, np) of the projected T and rho_v."""
+        import torch
+        Tc = torch.empty((self.ne, self.np), dtype=torch.float64, device=C.device)
+        Rc = torch.empty_like(Tc)
+        _check(self.L.dg_tri_split(self.h, self._coef(C, self.nvars), ct.c_void_p(Tc.data_ptr()),
+                                   ct.c_void_p(Rc.data_ptr()), ct.c_void_p(_stream(stream))))
+        return Tc, Rc
+
+    def rhs(self, C, out=None, stream=None):
+        import torch
+        out = torch.empty_like(C) if out is None else out
+        _check(self.L.dg_tri_rhs(self.h, self._coef(C, self.nvars), self._coef(out, self.nvars, "out"),
+                                 ct.c_void_p(_stream(stream))))
+        return out
+
+    def rk_step(self, C, dt: float, nsteps: int = 1, stream=None):
+        _check(self.L.dg_tri_rk_step(self.h, self._coef(C, self.nvars), float(dt), int(nsteps),
+                                     ct.c_void_p(_stream(stream))))
+        return C
+
+    def stats(self):
+        s = dg_stats()
+        st = self.L.dg_tri_get_stats(self.h, ct.byref(s))
+        return dict(status=st, splits=s.splits, nonconverged=s.nonconverged, max_iters=s.max_iters,
+                    nonfinite=s.nonfinite)
+
+    def reset_stats(self):
+        _check(self.L.dg_tri_reset_stats(self.h))
+
+    def timing(self, enable: bool = True):
+        _check(self.L.dg_tri_timing_enable(self.h, int(bool(enable))))
+
+    def timing_read(self, kclass: int):
+        ms, n = ct.c_double(), ct.c_longlong()
+        _check(self.L.dg_tri_timing_read(self.h, int(kclass), ct.byref(ms), ct.byref(n)))
+        return ms.value, n.value
+
+
+def for_tri_case(case, precision=DG_FP64, **over) -> DGTri:
+    """Triangulation handle + background for a synthetic triangle case (synth.tri_bubble)."""
+    p = default_params(g=case.g, rain=case.rain, vr_const=case.vr_const, precision=precision, **over)
+    dg = DGTri(case.mesh, case.nvars, p)
+    dg.set_background(case.bg["rho_d"], case.bg["rho_m"], case.bg["rho_r"], case.bg["E"])
     return dg

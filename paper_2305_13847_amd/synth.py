@@ -659,11 +659,14 @@ class TriCase:
 
 
 def tri_bubble(n=(64, 32), order=3, seed=7, nsteps=100, amp=2.0, centre=(10e3, 2e3), radius=2e3,
-               ratio=1.3, Ts=300.0, top=10e3, jitter=0.0) -> TriCase:
+               ratio=1.3, Ts=300.0, top=10e3, jitter=0.0, rain=False, vr=5.0, noise=0.0) -> TriCase:
     """The 2D moist rising bubble of ``moist_bubble`` on a triangulation.
 
-    Domain 20 km x `top`, periodic in x, slip walls in z, gravity on, no rain
-    (the shape of the paper's bubble run on triangles, Section 4.2).
+    Domain 20 km x `top`, periodic in x, slip walls in z, gravity on (the
+    shape of the paper's bubble run on triangles, Section 4.2).  With ``rain``
+    a Gaussian rain blob of 1e-3 kg/m^3 sits 1 km above the bubble and falls at
+    ``vr``; ``noise`` adds seeded relative noise of that level at the sample
+    points (the same draw for the same array of points).
     """
     mesh = tri_mesh(n, (0.0, 0.0), (20e3, top), (PERIODIC, WALL), order, jitter, seed)
     bgf = background(mesh.layers, Ts, lambda z: ratio + 0.0 * z)
@@ -678,9 +681,21 @@ def tri_bubble(n=(64, 32), order=3, seed=7, nsteps=100, amp=2.0, centre=(10e3, 2
         E1 = partitioned_energy(b["rho_d"], b["rho_m"], b["rho_r"], b["T"] + Tp)
         E0 = partitioned_energy(b["rho_d"], b["rho_m"], b["rho_r"], b["T"])
         z = np.zeros_like(th)
-        return np.ascontiguousarray(np.stack([z, z, z, z, E1 - E0]))
+        flds = [z, z.copy()]
+        if rain:
+            r2 = (X[0] - centre[0]) ** 2 + (X[1] - centre[1] - 1e3) ** 2
+            flds.append(1e-3 * np.exp(-r2 / 1e6))
+        flds += [z.copy(), z.copy(), E1 - E0]
+        if noise:
+            rng = np.random.default_rng(seed)
+            rho = b["rho_d"] + b["rho_m"]
+            scales = [b["rho_d"], b["rho_m"]] + ([1e-3 + 0.0 * rho] if rain else []) + [rho, rho, b["E"]]
+            for v, sc in enumerate(scales):
+                flds[v] = flds[v] + noise * sc * rng.standard_normal(th.shape)
+        return np.ascontiguousarray(np.stack(flds))
 
     h = float(np.min(mesh.h))
-    dt = float(0.2 * 0.5 * h / ((2 * order + 1) * (C_BOUND + 5.0)))
-    return TriCase("bubble-2d-p%d-%dx%dx2%s" % (order, n[0], n[1], "-jitter" if jitter else ""), mesh, 5, 0,
-                   C["g"], 0.0, bg, point_state, dt, nsteps, seed)
+    dt = float(0.2 * 0.5 * h / ((2 * order + 1) * (C_BOUND + 5.0 + (vr if rain else 0.0))))
+    return TriCase("%s-2d-p%d-%dx%dx2%s" % ("rain" if rain else "bubble", order, n[0], n[1],
+                                            "-jitter" if jitter else ""), mesh, 6 if rain else 5, int(rain),
+                   C["g"], vr if rain else 0.0, bg, point_state, dt, nsteps, seed)

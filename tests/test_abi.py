@@ -25,7 +25,8 @@ HEADER = os.path.join(ROOT, "include", "dg.h")
 
 
 def _declared():
-    text = open(HEADER).read()
+    inc = os.path.join(ROOT, "include")
+    text = "\n".join(open(os.path.join(inc, f)).read() for f in sorted(os.listdir(inc)) if f.endswith(".h"))
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     text = re.sub(r"//[^\n]*", "", text)
     return sorted(set(re.findall(r"^[A-Za-z_][\w \*]*?\b(dg_\w+)\s*\(", text, flags=re.M)))
@@ -52,6 +53,7 @@ PROBE = r"""
 #include <stddef.h>
 #include <stdio.h>
 #include "dg.h"
+#include "dg_tri.h"
 #define F(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
   printf("dg_mesh %zu\ndg_params %zu\ndg_stats %zu\n", sizeof(dg_mesh), sizeof(dg_params), sizeof(dg_stats));
@@ -60,6 +62,9 @@ int main(void) {
   F(dg_params, q_au) F(dg_params, precision) F(dg_params, rk) F(dg_params, newton_rtol)
   F(dg_params, newton_maxit) F(dg_params, sponge_zD) F(dg_params, sponge_alpha) F(dg_params, basis) F(dg_params, sip_gamma) F(dg_params, sip_sigma)
   F(dg_stats, splits) F(dg_stats, nonconverged) F(dg_stats, max_iters) F(dg_stats, nonfinite)
+  printf("dg_tri_mesh %zu\n", sizeof(dg_tri_mesh));
+  F(dg_tri_mesh, ne) F(dg_tri_mesh, xy) F(dg_tri_mesh, nb) F(dg_tri_mesh, nbf) F(dg_tri_mesh, z0)
+  F(dg_tri_mesh, dz) F(dg_tri_mesh, nz)
   return 0;
 }
 """
@@ -76,7 +81,8 @@ def test_struct_layouts_match_the_header():
             pytest.skip("cannot compile the header probe: " + r.stderr[-300:])
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
     got = dict(line.rsplit(" ", 1) for line in out.strip().splitlines())
-    structs = {"dg_mesh": lib.dg_mesh, "dg_params": lib.dg_params, "dg_stats": lib.dg_stats}
+    structs = {"dg_mesh": lib.dg_mesh, "dg_params": lib.dg_params, "dg_stats": lib.dg_stats,
+               "dg_tri_mesh": lib.dg_tri_mesh}
     for key, val in got.items():
         if "." in key:
             s, f = key.split(".")
@@ -115,3 +121,39 @@ def test_order_range_is_checked_before_the_device(dim, order):
     with pytest.raises(lib.DGError) as e:
         lib.DG(c.mesh, order, c.nvars, lib.params_for_case(c, lib.DG_FP64))
     assert e.value.status == lib.DG_EINVAL, str(e.value)
+
+
+def test_triangle_create_without_a_device_fails_loudly():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2305_13847_amd import synth
+    c = synth.tri_bubble(n=(4, 2), order=2)
+    with pytest.raises(lib.DGError) as e:
+        lib.for_tri_case(c)
+    assert "dg status" in str(e.value)
+
+
+@pytest.mark.parametrize("order", [0, 5])
+def test_triangle_order_range_is_checked_before_the_device(order):
+    from paper_2305_13847_amd import synth
+    c = synth.tri_bubble(n=(4, 2), order=2)
+    c.mesh.order = order
+    with pytest.raises(lib.DGError) as e:
+        lib.DGTri(c.mesh, c.nvars, lib.default_params())
+    assert e.value.status == lib.DG_EINVAL, str(e.value)
+
+
+def test_triangle_tables_are_checked_before_the_device():
+    from paper_2305_13847_amd import synth
+    c = synth.tri_bubble(n=(4, 2), order=2)
+    bad = synth.tri_mesh((4, 2), (0.0, 0.0), (20e3, 10e3), (0, 1), 2)
+    bad.nbf[0, 1] = (bad.nbf[0, 1] + 1) % 3          # no longer symmetric
+    with pytest.raises(lib.DGError) as e:
+        lib.DGTri(bad, c.nvars, lib.default_params())
+    assert e.value.status == lib.DG_EINVAL and "symmetric" in str(e.value)
+    flip = synth.tri_mesh((4, 2), (0.0, 0.0), (20e3, 10e3), (0, 1), 2)
+    flip.xy[3] = flip.xy[3][::-1].copy()              # clockwise
+    with pytest.raises(lib.DGError) as e:
+        lib.DGTri(flip, c.nvars, lib.default_params())
+    assert e.value.status == lib.DG_EINVAL and "counter-clockwise" in str(e.value)
