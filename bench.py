@@ -17,7 +17,8 @@ stage kernel: algorithmic bytes per launch / its HIP-event-timed duration
 against 8 TB/s) for FP32 bulk and for FP64 (the paper's precision), the same
 FP32 workload with the Rayleigh sponge, with the artificial diffusion, and in
 the paper's Legendre/Gauss basis (FP32 and FP64), the 2D moist bubble
-(128 x 64, Q4) in FP64 and FP32, the batched 64-member ensemble, and the FP64
+(128 x 64, Q4) in FP64 and FP32, the batched 64-member ensemble, the bubble on
+a triangulation (512 x 256 cells, two P3 triangles each), and the FP64
 CPU reference timed on a bounded sample of the 3D workload (one thread and
 all cores), with the per-field error of the GPU's FP32 bulk and FP64 runs
 against it.
@@ -133,6 +134,35 @@ def time_workload(case, precision, steps, warmup, replays, lib, torch, kernels=T
     st = dg.stats()
     out["newton_max_iters"] = st["max_iters"]
     out["status"] = st["status"]
+    dg.close()
+    return out
+
+
+def tri_alg_bytes(s_bytes: int, nvars: int, order: int, ne: int) -> float:
+    """Algorithmic bytes of one fused triangle stage launch: the coefficients
+    read and written (and U_n in one stage of four), the projected T and rho_v
+    read and written in FP64, and 60 bytes of geometry and neighbour table."""
+    npk = (order + 1) * (order + 2) // 2
+    return ne * (2.25 * s_bytes * nvars * npk + 4 * 8 * npk + 60)
+
+
+def time_tri(precision, steps, warmup, replays, lib, torch, synth, n=(512, 256), order=3):
+    """The 2D moist bubble on a triangulation of n[0] x n[1] cells (two
+    triangles each), P^k, projected onto the library's basis on the GPU."""
+    case = synth.tri_bubble(n=n, order=order, noise=1e-4)
+    dg = lib.for_tri_case(case, precision=precision)
+    C = dg.state(case.point_state)
+    step = lambda k: dg.rk_step(C, case.dt, k)
+    secs = timed_replays(step, steps, warmup, replays, torch)
+    med = float(np.median(secs))
+    dofs = C.numel()
+    out = dict(workload=case.name, dofs=dofs, elements=case.mesh.ne, dof_stage_per_s=dofs * 4 * steps / med,
+               ms_per_step=1e3 * med / steps)
+    out.update(kernel_pass(dg, step, max(2, steps // 2), lib, torch))
+    sb = 8 if precision == lib.DG_FP64 else 4
+    out["roofline"] = roofline("tri_stage_kernel<%s,%d,dry,stage>" % ("double" if sb == 8 else "float", order),
+                               out["stage_us"], tri_alg_bytes(sb, case.nvars, order, case.mesh.ne))
+    out["status"] = dg.stats()["status"]
     dg.close()
     return out
 
@@ -266,7 +296,8 @@ def main():
     ap.add_argument("--replays", type=int, default=5, help="timed replays (the median is reported)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU reference leg")
     ap.add_argument("--no-extra", action="store_true", help="skip the secondary workloads")
-    ap.add_argument("--only", choices=["fp32", "fp64", "gauss-fp32", "gauss-fp64", "sip-fp32"],
+    ap.add_argument("--only", choices=["fp32", "fp64", "gauss-fp32", "gauss-fp64", "sip-fp32", "tri-fp32",
+                                       "tri-fp64"],
                     help="time one 3D warm-rain variant only, without kernel timing (for profilers)")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MIB",
                     help="only copy a device buffer of this size (traffic-counter calibration)")
@@ -293,6 +324,14 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(3)
 
+    if args.only and args.only.startswith("tri"):
+        prec = lib.DG_FP64 if args.only.endswith("fp64") else lib.DG_FP32_BULK
+        case = synth.tri_bubble(n=(512, 256), order=3, noise=1e-4)
+        dg = lib.for_tri_case(case, precision=prec)
+        C = dg.state(case.point_state)
+        secs = timed_replays(lambda k: dg.rk_step(C, case.dt, k), args.steps, args.warmup, args.replays, torch)
+        print(json.dumps({"only": args.only, "ms_per_step": 1e3 * float(np.median(secs)) / args.steps}))
+        return
     if args.only:
         basis = "gauss" if args.only.startswith("gauss") else "lobatto"
         prec = lib.DG_FP64 if args.only.endswith("fp64") else lib.DG_FP32_BULK
@@ -348,6 +387,9 @@ def main():
             r = time_workload(bub, prec, 50, 5, args.replays, lib, torch)
             extra[nm] = {k: r[k] for k in ("dof_stage_per_s", "ms_per_step", "stage_us", "split_us")}
         extra["ensemble64_q3_fp32"] = time_ensemble(20, args.replays, lib, torch, synth)
+        # triangles (the simplicial P^k space): the 2D bubble on 512 x 256 x 2 triangles, P3
+        for prec, nm in ((lib.DG_FP32_BULK, "bubble2d_tri_p3_fp32"), (lib.DG_FP64, "bubble2d_tri_p3_fp64")):
+            extra[nm] = time_tri(prec, 10, 2, args.replays, lib, torch, synth)
     cpu = None
     if not args.no_cpu:
         import oracle as oracle_mod

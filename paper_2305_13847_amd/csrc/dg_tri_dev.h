@@ -12,6 +12,8 @@
 // the reconstruction of full densities and p', the split and the projected T
 // and rho_v in FP64.
 #pragma once
+#include <type_traits>
+
 #include "dg_device.h"
 
 namespace dgm {
@@ -93,8 +95,7 @@ __device__ __forceinline__ TriZ tri_z(const TriArgs& t, int e) {
 // Background (rho_d, rho_m, rho_r, E, p) at height z from layer l's
 // degree-K interpolant through its Gauss heights.
 template <typename R, int K>
-__device__ __forceinline__ void tri_bg(const TriArgs& t, int l, double z, double* b) {
-  const auto& T = ttab<R, K>();
+__device__ __forceinline__ void tri_bg(const TriArgs& t, const TriTab<R, K>& T, int l, double z, double* b) {
   const double xi = 2.0 * ((z - t.z0) * t.inv_dz - (double)l) - 1.0;
   double ell[K + 1];
 #pragma unroll
@@ -181,18 +182,60 @@ struct TriBlock {
 template <typename R, int K, int RAIN>
 struct TriLds {
   static constexpr int NV = Vars<2, RAIN>::NV, NP = TriShape<K>::NP, NQ = TriShape<K>::NQ;
-  static constexpr int EPB = TriBlock<K>::EPB;
+  static constexpr int NF = TriShape<K>::NF, EPB = TriBlock<K>::EPB;
+  static constexpr bool HAS_AUX = true;
+  // the reference tables (FP32; in FP64 they would halve the blocks per CU and
+  // stay in constant memory)
+  struct Empty {};
+  std::conditional_t<sizeof(R) == 4, TriTab<R, K>, Empty> tab;
   double aux[EPB][2][NP];   // projected T and rho_v of the stage input
   double ts[EPB][NQ][2];    // the split of the updated state at the volume points
   R c[EPB][NV][NP];         // coefficients of the stage input, then of its update
-  R pf[EPB][NQ][3 * NV];    // per volume point: w F.G0, w F.G1, w G; then per face point: w_f F_n
+  union {
+    R pf[EPB][NQ][3 * NV];  // per volume point: w F.G0, w F.G1, w G
+    struct {                // then the neighbours across the three faces
+      double aux[EPB][3][2][NP];
+      R c[EPB][3][NV][NP];
+    } nb;
+  } u;
+  R ff[EPB][3 * NF][NV];    // per face point: the weighted normal flux
 };
+
+// LDS of the split kernel: coefficients and the split values only
+template <typename R, int K, int RAIN>
+struct TriLdsSplit {
+  static constexpr int NV = Vars<2, RAIN>::NV, NP = TriShape<K>::NP, NQ = TriShape<K>::NQ;
+  static constexpr int EPB = TriBlock<K>::EPB;
+  static constexpr bool HAS_AUX = false;
+  struct Empty {};
+  std::conditional_t<sizeof(R) == 4, TriTab<R, K>, Empty> tab;
+  double ts[EPB][NQ][2];
+  R c[EPB][NV][NP];
+};
+
+// Copy the reference tables (a plain struct) from constant memory into LDS
+// (FP32 kernels), and the tables a kernel reads: the LDS copy or constant memory.
+template <typename R, int K, typename L>
+__device__ __forceinline__ void tri_copy_tab(L& S) {
+  if constexpr (sizeof(R) == 4) {
+    static_assert(sizeof(TriTab<R, K>) % 4 == 0, "tables are whole words");
+    const unsigned* s = reinterpret_cast<const unsigned*>(&ttab<R, K>());
+    unsigned* d = reinterpret_cast<unsigned*>(&S.tab);
+    for (int i = threadIdx.x; i < (int)(sizeof(TriTab<R, K>) / 4); i += blockDim.x) d[i] = s[i];
+  }
+}
+
+template <typename R, int K, typename L>
+__device__ __forceinline__ const TriTab<R, K>& tri_tab(const L& S) {
+  if constexpr (sizeof(R) == 4) return S.tab;
+  else return ttab<R, K>();
+}
 
 // Load the block's coefficients (and aux) into LDS with coalesced reads;
 // elements past the end repeat the last one (their results are never stored).
-template <typename R, int K, int RAIN>
-__device__ __forceinline__ void tri_load_block(TriLds<R, K, RAIN>& S, const TriArgs& t, long long e0,
-                                               const R* __restrict__ U, const double* __restrict__ aux) {
+template <typename R, int K, int RAIN, typename L>
+__device__ __forceinline__ void tri_load_block(L& S, const TriArgs& t, long long e0, const R* __restrict__ U,
+                                               const double* __restrict__ aux) {
   constexpr int NV = Vars<2, RAIN>::NV, NP = TriShape<K>::NP, EPB = TriBlock<K>::EPB;
   const size_t N = (size_t)t.ne * NP;
   for (int idx = threadIdx.x; idx < NV * EPB * NP; idx += blockDim.x) {
@@ -201,7 +244,7 @@ __device__ __forceinline__ void tri_load_block(TriLds<R, K, RAIN>& S, const TriA
     const long long e = min(e0 + le, (long long)t.ne - 1);
     S.c[le][v][m] = U[v * N + (size_t)e * NP + m];
   }
-  if (aux)
+  if constexpr (L::HAS_AUX)
     for (int idx = threadIdx.x; idx < 2 * EPB * NP; idx += blockDim.x) {
       const int v = idx / (EPB * NP), r = idx - v * (EPB * NP);
       const int le = r / NP, m = r - le * NP;
@@ -212,11 +255,11 @@ __device__ __forceinline__ void tri_load_block(TriLds<R, K, RAIN>& S, const TriA
 
 // The split of the block's state S.c at volume point q of element slot el
 // (thread (el, q)), written to S.ts; Tguess (optional) from S.aux.
-template <typename R, int K, int RAIN>
-__device__ __forceinline__ void tri_split_at(const KArgs& a, const TriArgs& t, TriLds<R, K, RAIN>& S, int el, int q,
-                                             const TriZ& g, bool guess, int* iters, int* bad) {
+template <typename R, int K, int RAIN, typename L>
+__device__ __forceinline__ void tri_split_at(const KArgs& a, const TriArgs& t, L& S, int el, int q, const TriZ& g,
+                                             int* iters, int* bad) {
   constexpr int NV = Vars<2, RAIN>::NV, NP = TriShape<K>::NP;
-  const auto& T = ttab<R, K>();
+  const auto& T = tri_tab<R, K>(S);
   double X[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -226,12 +269,12 @@ __device__ __forceinline__ void tri_split_at(const KArgs& a, const TriArgs& t, T
     X[v] = s;
   }
   double Tg = 0.0;
-  if (guess) {
+  if constexpr (L::HAS_AUX) {
 #pragma unroll
     for (int m = 0; m < NP; ++m) Tg += S.aux[el][0][m] * T.psid[q][m];
   }
   double b[5];
-  tri_bg<R, K>(t, g.layer, g.z0 + g.dz1 * T.rq[q] + g.dz2 * T.sq[q], b);
+  tri_bg<R, K>(t, T, g.layer, g.z0 + g.dz1 * T.rq[q] + g.dz2 * T.sq[q], b);
   double rv;
   const SplitOut o = tri_split_point<RAIN>(a, X, b, Tg, &rv);
   S.ts[el][q][0] = o.T;
@@ -242,11 +285,11 @@ __device__ __forceinline__ void tri_split_at(const KArgs& a, const TriArgs& t, T
 
 // The L2 projections of the split values S.ts onto P^k, by thread (el, j),
 // j < 2 NP (j < NP: T, else rho_v), stored to Tn / Rn.
-template <typename R, int K, int RAIN>
-__device__ __forceinline__ void tri_project_split(const TriLds<R, K, RAIN>& S, int el, int j, long long e, bool act,
+template <typename R, int K, int RAIN, typename L>
+__device__ __forceinline__ void tri_project_split(const L& S, int el, int j, long long e, bool act,
                                                   double* __restrict__ Tn, double* __restrict__ Rn) {
   constexpr int NP = TriShape<K>::NP, NQ = TriShape<K>::NQ;
-  const auto& T = ttab<R, K>();
+  const auto& T = tri_tab<R, K>(S);
   if (j >= 2 * NP) return;
   const int c = j >= NP ? 1 : 0, m = j - c * NP;
   double s = 0.0;
@@ -260,17 +303,18 @@ template <typename R, int K, int RAIN>
 __global__ void __launch_bounds__(256) tri_split_kernel(KArgs a, TriArgs t, const R* __restrict__ U,
                                                         double* __restrict__ Tn, double* __restrict__ Rn) {
   constexpr int NQ = TriShape<K>::NQ, EPB = TriBlock<K>::EPB, NT = TriBlock<K>::NT;
-  __shared__ TriLds<R, K, RAIN> S;
+  __shared__ TriLdsSplit<R, K, RAIN> S;
   const int tid = threadIdx.x;
   const bool lane = tid < NT;
   const int el = lane ? tid / NQ : 0, q = lane ? tid - el * NQ : 0;
   const long long e0 = (long long)blockIdx.x * EPB;
   const bool act = lane && e0 + el < t.ne;
   const long long e = min(e0 + el, (long long)t.ne - 1);
+  tri_copy_tab<R, K>(S);
   tri_load_block<R, K, RAIN>(S, t, e0, U, nullptr);
   __syncthreads();
   int it = 0, bd = 0;
-  if (lane) tri_split_at<R, K, RAIN>(a, t, S, el, q, tri_z(t, (int)e), false, &it, &bd);
+  if (lane) tri_split_at<R, K, RAIN>(a, t, S, el, q, tri_z(t, (int)e), &it, &bd);
   __syncthreads();
   if (lane) tri_project_split<R, K, RAIN>(S, el, q, e, act, Tn, Rn);
   record_stats(a, act ? it : 0, act ? bd : 0);
@@ -288,7 +332,7 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
   constexpr int NV = V::NV, NP = TriShape<K>::NP, NQ = TriShape<K>::NQ, NF = TriShape<K>::NF;
   constexpr int EPB = TriBlock<K>::EPB, NT = TriBlock<K>::NT;
   __shared__ TriLds<R, K, RAIN> S;
-  const auto& T = ttab<R, K>();
+  const auto& T = tri_tab<R, K>(S);
   const int tid = threadIdx.x;
   const bool lane = tid < NT;
   const int el = lane ? tid / NQ : 0, q = lane ? tid - el * NQ : 0;
@@ -297,6 +341,35 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
   const int e = (int)min(e0 + el, (long long)t.ne - 1);
   const size_t N = (size_t)t.ne * NP;
 
+  // the neighbours' coefficients across the three faces of the block's
+  // elements, read now (coalesced runs of NP values) and parked in LDS once
+  // the volume phase has released its storage
+  constexpr int NNC = (EPB * 3 * NV * NP + 255) / 256, NNA = (EPB * 3 * 2 * NP + 255) / 256;
+  R nreg[NNC];
+  double areg[NNA];
+#pragma unroll
+  for (int k = 0; k < NNC; ++k) {
+    const int idx = tid + 256 * k;
+    nreg[k] = R(0);
+    if (idx < EPB * 3 * NV * NP) {
+      const int m = idx % NP, r = idx / NP, v = r % NV, r2 = r / NV, f = r2 % 3, le = r2 / 3;
+      const long long ee = min(e0 + le, (long long)t.ne - 1);
+      const int nb = t.nbr[(size_t)ee * 3 + f];
+      if (nb >= 0) nreg[k] = U[v * N + (size_t)(nb >> 2) * NP + m];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NNA; ++k) {
+    const int idx = tid + 256 * k;
+    areg[k] = 0.0;
+    if (idx < EPB * 3 * 2 * NP) {
+      const int m = idx % NP, r = idx / NP, v = r % 2, r2 = r / 2, f = r2 % 3, le = r2 / 3;
+      const long long ee = min(e0 + le, (long long)t.ne - 1);
+      const int nb = t.nbr[(size_t)ee * 3 + f];
+      if (nb >= 0) areg[k] = aux[v * N + (size_t)(nb >> 2) * NP + m];
+    }
+  }
+  tri_copy_tab<R, K>(S);
   tri_load_block<R, K, RAIN>(S, t, e0, U, aux);
 
   // geometry: A = [V1 - V0, V2 - V0], G = A^{-T}
@@ -324,7 +397,7 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
       Rq += S.aux[el][1][m] * T.psid[q][m];
     }
     double b[5];
-    tri_bg<R, K>(t, g.layer, g.z0 + g.dz1 * T.rq[q] + g.dz2 * T.sq[q], b);
+    tri_bg<R, K>(t, T, g.layer, g.z0 + g.dz1 * T.rq[q] + g.dz2 * T.sq[q], b);
     Pt<R, 2, RAIN> p;
     eval_core<R, 2, RAIN>(a, Uq, Tq, Rq, RAIN ? rho_vs(a, Tq) : 0.0, b[0], b[1], b[2], b[3], b[4], p);
     const R wq = T.w[q];
@@ -336,26 +409,44 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
     sources<R, 2, RAIN>(a, Uq, p, Gs);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-      S.pf[el][q][v] = Fr[v];
-      S.pf[el][q][NV + v] = Fs[v];
-      S.pf[el][q][2 * NV + v] = wq * Gs[v];
+      S.u.pf[el][q][v] = Fr[v];
+      S.u.pf[el][q][NV + v] = Fs[v];
+      S.u.pf[el][q][2 * NV + v] = wq * Gs[v];
     }
   }
   __syncthreads();
 
-  // modes: (F, grad psi_m) + (G, psi_m) over the volume points
-  R acc[NV];
+  // modes: (F, grad psi_m) + (G, psi_m) over the volume points.  NQ = 2 NP,
+  // so thread (el, q) takes mode m = q mod NP for the variables v = par,
+  // par + 2, ... with par = q / NP.
+  static_assert(NQ == 2 * NP, "the Duffy rule has twice as many points as P^k has modes");
+  constexpr int NH = (NV + 1) / 2;
+  const int m = q % NP, par = q / NP;
+  R acc[NH];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = R(0);
-  if (lane && q < NP) {
-    const int m = q;
+  for (int h = 0; h < NH; ++h) acc[h] = R(0);
+  if (lane) {
 #pragma unroll 2
     for (int qq = 0; qq < NQ; ++qq) {
       const R dr = T.dr[qq][m], ds = T.ds[qq][m], ps = T.psi[qq][m];
 #pragma unroll
-      for (int v = 0; v < NV; ++v)
-        acc[v] += S.pf[el][qq][v] * dr + S.pf[el][qq][NV + v] * ds + S.pf[el][qq][2 * NV + v] * ps;
+      for (int h = 0; h < NH; ++h) {
+        const int v = par + 2 * h;
+        if (v < NV)
+          acc[h] += S.u.pf[el][qq][v] * dr + S.u.pf[el][qq][NV + v] * ds + S.u.pf[el][qq][2 * NV + v] * ps;
+      }
     }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < NNC; ++k) {
+    const int idx = tid + 256 * k;
+    if (idx < EPB * 3 * NV * NP) (&S.u.nb.c[0][0][0][0])[idx] = nreg[k];
+  }
+#pragma unroll
+  for (int k = 0; k < NNA; ++k) {
+    const int idx = tid + 256 * k;
+    if (idx < EPB * 3 * 2 * NP) (&S.u.nb.aux[0][0][0][0])[idx] = areg[k];
   }
   __syncthreads();
 
@@ -385,7 +476,7 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
       Rm += S.aux[el][1][m] * T.psifd[f][i][m];
     }
     double b[5];
-    tri_bg<R, K>(t, g.layer, z, b);
+    tri_bg<R, K>(t, T, g.layer, z, b);
     const double rvsm = RAIN ? rho_vs(a, Tm) : 0.0;
     {
       Pt<R, 2, RAIN> pm;
@@ -411,16 +502,16 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
         for (int v = 0; v < NV; ++v) {
           R s = R(0);
 #pragma unroll
-          for (int m = 0; m < NP; ++m) s += U[v * N + (size_t)e2 * NP + m] * T.psif[f2][i2][m];
+          for (int m = 0; m < NP; ++m) s += S.u.nb.c[el][f][v][m] * T.psif[f2][i2][m];
           Up[v] = s;
         }
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
-          Tp += aux[(size_t)e2 * NP + m] * T.psifd[f2][i2][m];
-          Rp += aux[N + (size_t)e2 * NP + m] * T.psifd[f2][i2][m];
+          Tp += S.u.nb.aux[el][f][0][m] * T.psifd[f2][i2][m];
+          Rp += S.u.nb.aux[el][f][1][m] * T.psifd[f2][i2][m];
         }
         double b2[5];
-        tri_bg<R, K>(t, tri_z(t, e2).layer, z, b2);
+        tri_bg<R, K>(t, T, tri_z(t, e2).layer, z, b2);
         eval_core<R, 2, RAIN>(a, Up, Tp, Rp, RAIN ? rho_vs(a, Tp) : 0.0, b2[0], b2[1], b2[2], b2[3], b2[4], pp);
       }
       flux_dir<R, RAIN>(pp, nx, nz, Fp);
@@ -430,27 +521,32 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
     const R wgt = (R)(len * idet) * T.wf[i];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-      S.pf[el][q][v] = wgt * (R(0.5) * (Fm[v] + Fp[v]) + R(0.5) * L * (Um[v] - Up[v]));
+      S.ff[el][q][v] = wgt * (R(0.5) * (Fm[v] + Fp[v]) + R(0.5) * L * (Um[v] - Up[v]));
   }
   __syncthreads();
 
   // modes: minus the face integrals, then the update
-  if (lane && q < NP) {
-    const int m = q;
+  if (lane) {
 #pragma unroll
     for (int j = 0; j < 3 * NF; ++j) {
       const R ps = T.psif[j / NF][j % NF][m];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) acc[v] -= S.pf[el][j][v] * ps;
+      for (int h = 0; h < NH; ++h) {
+        const int v = par + 2 * h;
+        if (v < NV) acc[h] -= S.ff[el][j][v] * ps;
+      }
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      R x = acc[v];
-      if (MODE != 0) {
-        x = (R)c1 * S.c[el][v][m] + (R)c2dt * acc[v];
-        if (c0 != 0.0) x += (R)c0 * U0[v * N + (size_t)e * NP + m];
+    for (int h = 0; h < NH; ++h) {
+      const int v = par + 2 * h;
+      if (v < NV) {
+        R x = acc[h];
+        if (MODE != 0) {
+          x = (R)c1 * S.c[el][v][m] + (R)c2dt * acc[h];
+          if (c0 != 0.0) x += (R)c0 * U0[v * N + (size_t)e * NP + m];
+        }
+        S.c[el][v][m] = x;
       }
-      S.c[el][v][m] = x;
     }
   }
   __syncthreads();
@@ -462,7 +558,7 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
   if constexpr (MODE == 2) {
     // the split of the updated state for the next stage (Section 3.4)
     int it = 0, bd = 0;
-    if (lane) tri_split_at<R, K, RAIN>(a, t, S, el, q, g, true, &it, &bd);
+    if (lane) tri_split_at<R, K, RAIN>(a, t, S, el, q, g, &it, &bd);
     __syncthreads();
     if (lane) tri_project_split<R, K, RAIN>(S, el, q, e, act, Tn, Rn);
     record_stats(a, act ? it : 0, act ? bd : 0);
