@@ -43,24 +43,26 @@ HBM_PEAK_GBS = 8000.0
 # (the stored pair (T, rho_vs(T)) moves twice this)
 WARM_START_BYTES_PER_NODE = 16
 
-# the sources the FP32 fused stage kernel is compiled from
-STAGE_SOURCES = ("dg_common.h", "dg_device.h", "dg_kernels.h", "dg_q3.h", "dg_f32.hip")
+# the sources the fused stage kernels are compiled from (both precisions)
+STAGE_SOURCES = ("dg_common.h", "dg_device.h", "dg_kernels.h", "dg_q3.h", "dg_f32.hip", "dg_f64.hip")
+TRI_SOURCES = ("dg_common.h", "dg_device.h", "dg_tri_dev.h", "dg_tri_api.hip")
 
 MAIN = "rain-3d-q3-64x64x32"
+TRI = "bubble-2d-p3-512x256x2"
 
 
-def csrc_hash() -> str:
-    """Hash of the stage kernel's sources: a committed traffic figure is used
-    only while it matches."""
+def csrc_hash(sources=STAGE_SOURCES) -> str:
+    """Hash of a kernel's sources: a committed traffic figure is used only
+    while it matches."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2305_13847_amd", "csrc")
-    for f in STAGE_SOURCES:
+    for f in sources:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_for(kernel: str, workload: str):
+def traffic_for(kernel: str, workload: str, sources=STAGE_SOURCES):
     """HBM bytes per launch from committed rocprof counter runs, if current."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
@@ -68,7 +70,7 @@ def traffic_for(kernel: str, workload: str):
     with open(path) as f:
         rec = json.load(f)
     ent = rec.get(workload, {}).get(kernel)
-    if not ent or ent.get("csrc_hash") != csrc_hash():
+    if not ent or ent.get("csrc_hash") != csrc_hash(sources):
         return None
     return ent.get("bytes_per_launch")
 
@@ -161,7 +163,8 @@ def time_tri(precision, steps, warmup, replays, lib, torch, synth, n=(512, 256),
     out.update(kernel_pass(dg, step, max(2, steps // 2), lib, torch))
     sb = 8 if precision == lib.DG_FP64 else 4
     out["roofline"] = roofline("tri_stage_kernel<%s,%d,dry,stage>" % ("double" if sb == 8 else "float", order),
-                               out["stage_us"], tri_alg_bytes(sb, case.nvars, order, case.mesh.ne))
+                               out["stage_us"], tri_alg_bytes(sb, case.nvars, order, case.mesh.ne),
+                               traffic_for("stage", "%s-fp%d" % (case.name, 8 * sb), TRI_SOURCES))
     out["status"] = dg.stats()["status"]
     dg.close()
     return out

@@ -147,10 +147,12 @@ static bool tri_dispatch(int K, int rain, F&& f) {
 
 static unsigned tri_blocks(long long n) { return (unsigned)((n + 63) / 64); }
 
-// blocks of the point-per-thread kernels: EPB elements each
+// blocks of the point-per-thread kernels: EPB elements each, rounded up to a
+// multiple of the 8 XCDs (tri_first_element)
 template <int K>
 static unsigned tri_grid(long long ne) {
-  return (unsigned)((ne + TriBlock<K>::EPB - 1) / TriBlock<K>::EPB);
+  const long long nb = (ne + TriBlock<K>::EPB - 1) / TriBlock<K>::EPB;
+  return (unsigned)(((nb + 7) / 8) * 8);
 }
 
 extern "C" dg_status dg_tri_create(const dg_tri_mesh* m, int order, int nvars, const dg_params* p, dg_tri** out) {

@@ -201,6 +201,19 @@ struct TriLds {
   R ff[EPB][3 * NF][NV];    // per face point: the weighted normal flux
 };
 
+// First element of this block.  Consecutive blocks go round-robin to the 8
+// XCDs; XCD x takes the contiguous block range [x per, (x+1) per), so an
+// element and its neighbours in the rows above and below share an L2.  The
+// grid is 8 per blocks; a block past the end returns -1 (uniformly).
+template <int K>
+__device__ __forceinline__ long long tri_first_element(int ne) {
+  constexpr int EPB = TriBlock<K>::EPB;
+  const int nblocks = (ne + EPB - 1) / EPB;
+  const int per = (nblocks + 7) >> 3;
+  const int b = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  return b < nblocks ? (long long)b * EPB : -1;
+}
+
 // LDS of the split kernel: coefficients and the split values only
 template <typename R, int K, int RAIN>
 struct TriLdsSplit {
@@ -307,7 +320,8 @@ __global__ void __launch_bounds__(256) tri_split_kernel(KArgs a, TriArgs t, cons
   const int tid = threadIdx.x;
   const bool lane = tid < NT;
   const int el = lane ? tid / NQ : 0, q = lane ? tid - el * NQ : 0;
-  const long long e0 = (long long)blockIdx.x * EPB;
+  const long long e0 = tri_first_element<K>(t.ne);
+  if (e0 < 0) return;
   const bool act = lane && e0 + el < t.ne;
   const long long e = min(e0 + el, (long long)t.ne - 1);
   tri_copy_tab<R, K>(S);
@@ -336,7 +350,8 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
   const int tid = threadIdx.x;
   const bool lane = tid < NT;
   const int el = lane ? tid / NQ : 0, q = lane ? tid - el * NQ : 0;
-  const long long e0 = (long long)blockIdx.x * EPB;
+  const long long e0 = tri_first_element<K>(t.ne);
+  if (e0 < 0) return;
   const bool act = lane && e0 + el < t.ne;
   const int e = (int)min(e0 + el, (long long)t.ne - 1);
   const size_t N = (size_t)t.ne * NP;
