@@ -44,7 +44,8 @@ HBM_PEAK_GBS = 8000.0
 WARM_START_BYTES_PER_NODE = 16
 
 # the sources the fused stage kernels are compiled from (both precisions)
-STAGE_SOURCES = ("dg_common.h", "dg_device.h", "dg_kernels.h", "dg_q3.h", "dg_f32.hip", "dg_f64.hip")
+STAGE_SOURCES = ("dg_common.h", "dg_device.h", "dg_kernels.h", "dg_q3.h", "dg_f32.hip", "dg_f64.hip",
+                 "dg_launch.h", "dg_api.hip")
 TRI_SOURCES = ("dg_common.h", "dg_device.h", "dg_tri_dev.h", "dg_tri_api.hip")
 
 MAIN = "rain-3d-q3-64x64x32"

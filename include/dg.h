@@ -274,16 +274,16 @@ dg_status dg_set_launch(dg_handle* h, int elems_per_block, int persist_per_cu);
 dg_status dg_get_launch(const dg_handle* h, int* elems_per_block, int* persist_per_cu);
 
 /* Order of the work items (3D handles; 2D items are always in element
- * order): 0 (default) y-bands of rows with z inside a band, so the elements
- * above and below an item were visited shortly before it; 1 plain element
- * order; 2 y-bands twice as wide.  Results do not depend on it.  Not a hot
- * call: synchronises.  DG_EINVAL for another value. */
+ * order): 0 y-bands of rows with z inside a band, so the elements above and
+ * below an item were visited shortly before it; 1 plain element order; 2
+ * (default) and 3 y-bands twice and four times as wide.  Results do not depend
+ * on it.  Not a hot call: synchronises.  DG_EINVAL for another value. */
 dg_status dg_set_item_order(dg_handle* h, int order);
 dg_status dg_get_item_order(const dg_handle* h, int* order);
 
 /* Autotuner: times nsteps RK steps of a copy of U (device) for every
  * candidate geometry (elements per block {max, max/2, max/4} x persistent
- * blocks per CU {0, 1, 2, 4} x item order {0, 1, 2} in 3D), keeps the
+ * blocks per CU {0, 1, 2, 4} x item order {0, 1, 2, 3} in 3D), keeps the
  * fastest and reports it (any output pointer may be NULL; best_ms is per
  * step; the order is read back with dg_get_item_order).  U is not modified. */
 dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, int nsteps, int* best_epb,

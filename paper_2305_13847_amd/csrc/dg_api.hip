@@ -124,7 +124,7 @@ struct dg_handle {
   // launch geometry
   int epb = 1;                   // elements per block
   int persist = 0;               // persistent blocks per CU (0: one block per item)
-  int item_order = 0;            // order of the work items (build_items)
+  int item_order = 2;            // order of the work items (build_items); 2 measured fastest on Q3 3D
   int ncu = 256;
   long long items_cap = 0;       // device capacity of the item table
   // captured multi-step graph
@@ -396,7 +396,8 @@ static void build_items(dg_handle* h, int epb, int order = -1) {
       // elements above and below an item were visited at most ~64 items
       // earlier and are still in the XCD's L2 when their faces are read.
       const int per_row = (md.n[0] + epb - 1) / epb;
-      const int by = std::max(1, std::min(md.n[1], (order == 2 ? 128 : 64) / std::max(1, per_row)));
+      const int span = order == 3 ? 256 : (order == 2 ? 128 : 64);
+      const int by = std::max(1, std::min(md.n[1], span / std::max(1, per_row)));
       auto key = [&](const Item& it) {
         const int c1 = it.c12 & 0xffff, c2 = it.c12 >> 16;
         return std::make_tuple(c1 / by, c2, c1 % by, it.c0);
@@ -1186,7 +1187,7 @@ extern "C" dg_status dg_set_launch(dg_handle* h, int epb, int persist) {
 
 extern "C" dg_status dg_set_item_order(dg_handle* h, int order) {
   if (!h) return fail(DG_EINVAL, "null handle");
-  if (order < 0 || order > 2) return fail(DG_EINVAL, "item order must be 0, 1 or 2");
+  if (order < 0 || order > 3) return fail(DG_EINVAL, "item order must be 0, 1, 2 or 3");
   HIP_TRY(hipDeviceSynchronize());
   if (order != h->item_order) {
     build_items(h, h->epb, order);
@@ -1222,7 +1223,7 @@ extern "C" dg_status dg_autotune(dg_handle* h, const void* U, const double* dt, 
   const int emax = elems_per_block(h->order, h->dim, h->prec == DG_FP64);
   const int cand_e[3] = {emax, emax / 2, emax / 4};
   const int cand_p[4] = {0, 1, 2, 4};
-  const int norders = h->dim == 3 ? 3 : 1;   // 2D items are always in element order
+  const int norders = h->dim == 3 ? 4 : 1;   // 2D items are always in element order
   void* W = h->stage_x[0];
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
