@@ -182,3 +182,27 @@ def test_rhs_rejects_aliasing():
     o, C, dg, Cg = _pair(c, 0)
     with pytest.raises(lib.DGError):
         dg.rhs(Cg, out=Cg)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-5)])
+def test_dry_mass_is_conserved_at_benchmark_size(prec, tol):
+    # periodic in x, slip walls in z: the dry mass sum_e det A_e c_0 / sqrt(2)
+    # (the mean mode of the orthonormal basis) is conserved by every step
+    lib = _lib()
+    c = synth.tri_bubble(n=(512, 256), order=3, noise=1e-4)
+    dg = lib.for_tri_case(c, precision=prec)
+    C = dg.state(c.point_state)
+    xy = c.mesh.xy
+    det = torch.tensor((xy[:, 1, 0] - xy[:, 0, 0]) * (xy[:, 2, 1] - xy[:, 0, 1])
+                       - (xy[:, 2, 0] - xy[:, 0, 0]) * (xy[:, 1, 1] - xy[:, 0, 1]), device="cuda")
+
+    def masses(X):
+        return [float(torch.sum(det * X[v, :, 0].double())) / np.sqrt(2.0) for v in (0, 1)]
+    # relative to the summed magnitude of the perturbation's element masses
+    scale = [float(torch.sum(torch.abs(det * C[v, :, 0].double()))) / np.sqrt(2.0) for v in (0, 1)]
+    m0 = masses(C)
+    dg.rk_step(C, c.dt, 5)
+    m1 = masses(C)
+    print("mass before/after", m0, m1, "scale", scale)
+    assert all(abs(a - b) < tol * sc for a, b, sc in zip(m0, m1, scale)), (m0, m1, scale)
+    assert dg.stats()["status"] == 0
