@@ -9,9 +9,11 @@
 //
 // Per element and RK stage (Section 3.2 weak form, Section 3.3 mass and
 // update, Section 3.4 split):
-//   1. load U, (T, rho_vs) of every node; issue the loads of the neighbour
-//      traces of the first face pass at once (their addresses depend on the
-//      element only);
+//   1. load U, (T, rho_vs) of every node, and the background at the
+//      element's heights and the neighbours' face heights into a small LDS
+//      table; issue the loads of the neighbour traces of the first face pass
+//      at once (their addresses depend on the element only), and those of the
+//      second pass before the first pass's arithmetic;
 //   2. evaluate the point state (FP64 reconstruction of p' and rho e), stage
 //      F_x, F_y, F_z, U and the wave speeds in LDS;
 //   3. volume term from the LDS lines, slip walls and sources by each node;
@@ -84,6 +86,17 @@ __device__ __forceinline__ void volume_q3(const MemberDesc& md, int li, int lj, 
   }
 }
 
+// eval_point with the background taken from a wavefront's LDS table
+// (fields rho_d, rho_m, rho_r, E, p; column h)
+template <typename R, int D, int RAIN>
+__device__ __forceinline__ void eval_tab(const KArgs& a, const R* Uq, double T, double rvs, const double (*sB)[6],
+                                         int h, Pt<R, D, RAIN>& q) {
+  using V = Vars<D, RAIN>;
+  const double bm = sB[1][h];
+  const double rv = fmin(rvs, bm + (double)Uq[V::RM]);
+  eval_core<R, D, RAIN>(a, Uq, T, rv, rvs, sB[0][h], bm, RAIN ? sB[2][h] : 0.0, sB[3][h], sB[4][h], q);
+}
+
 template <typename R, int RAIN, int MODE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(min_waves<R>())))
 rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
@@ -99,6 +112,9 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   __shared__ R sF_all[WPB][D][NV][NP];
   __shared__ R sU_all[WPB][NV][NP];
   __shared__ R sL_all[WPB][D][NP];
+  // background (rho_d, rho_m, rho_r, E, p) at the element's four heights and
+  // at the face heights of the neighbours below and above
+  __shared__ double sB_all[WPB][5][6];
   __shared__ R sD[P1 * P1];
   if (threadIdx.x < P1 * P1) sD[threadIdx.x] = (R)a.Dhat[threadIdx.x];
   __syncthreads();   // the only block-wide barrier: the shared D-hat table
@@ -115,6 +131,7 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   R(*sF)[NV][NP] = sF_all[w];
   R(*sU)[NP] = sU_all[w];
   R(*sL)[NP] = sL_all[w];
+  double(*sB)[6] = sB_all[w];
 
   // element (scalar): coordinates, neighbours per (direction, side), walls
   const ElemCoord<D> ec = item_coord<D>(md, item, w);
@@ -164,6 +181,15 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   const int en1 = t1s ? nbe[2][1] : nbe[2][0];
   const unsigned gn1 = (!a1 || w1) ? g : (unsigned)(md.eoff + en1) * NP + nn1;
 
+  // background table: lane 6 f + h loads field f at height h (issued with the
+  // own loads, stored after the evaluation)
+  double bgt = 0.0;
+  {
+    const int f = lane / 6, h = lane - 6 * (lane / 6);
+    const int izt = h < 4 ? izb + h : (h == 4 ? izn_lo : izn_hi);
+    const double* src = f == 0 ? a.bg_rd : (f == 1 ? a.bg_rm : (f == 2 ? a.bg_rr : (f == 3 ? a.bg_E : a.bg_p)));
+    if (lane < 30 && (RAIN || f != 2)) bgt = src[izt];
+  }
   // 1. own state
   R Uq[NV];
 #pragma unroll
@@ -190,6 +216,7 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   sL[0][lane] = wave_speed<R, D, RAIN, 0>(q);
   sL[1][lane] = wave_speed<R, D, RAIN, 1>(q);
   sL[2][lane] = wave_speed<R, D, RAIN, 2>(q);
+  if (lane < 30) (&sB[0][0])[lane] = bgt;
   // the neighbour traces of the first face pass: in flight during the volume term
   R Un0[NV];
 #pragma unroll
@@ -211,12 +238,17 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   sources<R, D, RAIN>(a, Uq, q, Rv);
   wave_lds_sync();   // the volume term has read sF before the faces overwrite it
 
+  // the neighbour traces of the second face pass: in flight during the first
+  R Un1[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) Un1[v] = ld(U, N, v, gn1);
+  const double Tn1 = ld(auxT, N, 0, gn1), rvsn1 = ld(auxS, N, 0, gn1);
   // 4. face passes: the lifted Lax-Friedrichs correction replaces F_J at the
   // own node: +-(lift/2)(F + F_n) + (lift/2) Lambda (U_n - U), + on the minus face
   const R half = R(0.5);
   if (!w0) {
     Pt<R, D, RAIN> qn;
-    eval_point<R, D, RAIN>(a, Un0, Tn0, rvsn0, izb + t0b, qn);
+    eval_tab<R, D, RAIN>(a, Un0, Tn0, rvsn0, sB, t0b, qn);
     R Fn[NV];
     flux_h<R, RAIN>(qn, t0x, Fn);
     const R ln = fabs(t0x ? qn.u[0] : qn.u[1]) + qn.cm;
@@ -224,7 +256,8 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
     const R lo = sL[J][n0];
     const bool own = t0s ? (lo >= ln) : !(ln >= lo);
     const R Lam = own ? lo : ln;
-    const R lift = t0x ? (R)md.lift[0][t0s] : (R)md.lift[1][t0s];
+    const double l00 = md.lift[0][0], l01 = md.lift[0][1], l10 = md.lift[1][0], l11 = md.lift[1][1];
+    const R lift = (R)(t0x ? (t0s ? l01 : l00) : (t0s ? l11 : l10));
     const R hl = half * lift;
     const R kf = t0s ? -hl : hl;
     const R kj = hl * Lam;
@@ -232,20 +265,17 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
     for (int v = 0; v < NV; ++v) sF[J][v][n0] = fma(kf, sF[J][v][n0] + Fn[v], kj * (Un0[v] - sU[v][n0]));
   }
   {
-    R Un1[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) Un1[v] = ld(U, N, v, gn1);
-    const double Tn1 = ld(auxT, N, 0, gn1), rvsn1 = ld(auxS, N, 0, gn1);
     if (a1 && !w1) {
       Pt<R, D, RAIN> qn;
-      eval_point<R, D, RAIN>(a, Un1, Tn1, rvsn1, t1s ? izn_hi : izn_lo, qn);
+      eval_tab<R, D, RAIN>(a, Un1, Tn1, rvsn1, sB, t1s ? 5 : 4, qn);
       R Fn[NV];
       flux<R, D, RAIN, 2>(qn, Fn);
       const R ln = wave_speed<R, D, RAIN, 2>(qn);
       const R lo = sL[2][n1];
       const bool own = t1s ? (lo >= ln) : !(ln >= lo);
       const R Lam = own ? lo : ln;
-      const R hl = half * (R)md.lift[2][t1s];
+      const double l20 = md.lift[2][0], l21 = md.lift[2][1];
+      const R hl = half * (R)(t1s ? l21 : l20);
       const R kf = t1s ? -hl : hl;
       const R kj = hl * Lam;
 #pragma unroll
@@ -260,10 +290,10 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
     for (int v = 0; v < NV; ++v) U0q[v] = ld(U0, N, v, g);
   }
   if (MODE == 2) {
-    bg[0] = a.bg_rd[iz];
-    bg[1] = a.bg_rm[iz];
-    if (RAIN) bg[2] = a.bg_rr[iz];
-    bg[3] = a.bg_E[iz];
+    bg[0] = sB[0][ll];
+    bg[1] = sB[1][ll];
+    if (RAIN) bg[2] = sB[2][ll];
+    bg[3] = sB[3][ll];
   }
   wave_lds_sync();
 

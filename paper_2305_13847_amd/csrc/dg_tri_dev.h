@@ -199,6 +199,8 @@ struct TriLds {
     } nb;
   } u;
   R ff[EPB][3 * NF][NV];    // per face point: the weighted normal flux
+  TriZ fz[EPB];             // heights of the vertices and background layer
+  R fn[EPB][3][3];          // per face: n_x, n_z, |e_f| / det A
 };
 
 // First element of this block.  Consecutive blocks go round-robin to the 8
@@ -393,6 +395,16 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
   const double a00 = xv[2] - xv[0], a01 = xv[4] - xv[0], a10 = g.dz1, a11 = g.dz2;
   const double det = a00 * a11 - a01 * a10;
   const double idet = 1.0 / det;
+  // the face geometry, for whichever threads take the element's face points
+  if (lane && q < 3) {
+    const double ex = q == 0 ? a00 : (q == 1 ? a01 - a00 : -a01);
+    const double ez = q == 0 ? a10 : (q == 1 ? a11 - a10 : -a11);
+    const double len = sqrt(ex * ex + ez * ez);
+    S.fn[el][q][0] = (R)(ez / len);
+    S.fn[el][q][1] = (R)(-ex / len);
+    S.fn[el][q][2] = (R)(len * idet);
+    if (q == 0) S.fz[el] = g;
+  }
   __syncthreads();
 
   // volume point q: flux along the columns of A^{-T} and sources, weighted
@@ -465,33 +477,37 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
   }
   __syncthreads();
 
-  // face point j = f NF + i: the Lax-Friedrichs flux against the neighbour's
-  // trace (or the slip-wall ghost), weighted by |e_f| / det A and w_i / 2
-  if (lane && q < 3 * NF) {
-    const int f = q / NF, i = q - f * NF;
-    const double ex = f == 0 ? a00 : (f == 1 ? a01 - a00 : -a01);
-    const double ez = f == 0 ? a10 : (f == 1 ? a11 - a10 : -a11);
-    const double len = sqrt(ex * ex + ez * ez);
-    const R nx = (R)(ez / len), nz = (R)(-ex / len);
-    const int nb = t.nbr[(size_t)e * 3 + f];
+  // face point j = f NF + i of element slot fe: the Lax-Friedrichs flux
+  // against the neighbour's trace (or the slip-wall ghost), weighted by
+  // |e_f| / det A and w_i / 2.  The EPB 3 NF face tasks go to the block's
+  // first threads, so whole wavefronts skip this phase instead of every
+  // wavefront running it with idle lanes.
+  static_assert(EPB * 3 * NF <= 256, "face tasks exceed the block");
+  if (tid < EPB * 3 * NF) {
+    const int fe = tid / (3 * NF), j = tid - fe * (3 * NF);
+    const int f = j / NF, i = j - f * NF;
+    const int ef = (int)min(e0 + fe, (long long)t.ne - 1);
+    const TriZ gf = S.fz[fe];
+    const R nx = S.fn[fe][f][0], nz = S.fn[fe][f][1];
+    const int nb = t.nbr[(size_t)ef * 3 + f];
     const bool wall = nb < 0;
-    const double z = g.z0 + g.dz1 * T.rf[f][i] + g.dz2 * T.sf[f][i];
+    const double z = gf.z0 + gf.dz1 * T.rf[f][i] + gf.dz2 * T.sf[f][i];
     R Um[NV], Up[NV], Fm[NV], Fp[NV], lm, lp;
     double Tm = 0.0, Rm = 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
       R s = R(0);
 #pragma unroll
-      for (int m = 0; m < NP; ++m) s += S.c[el][v][m] * T.psif[f][i][m];
+      for (int m = 0; m < NP; ++m) s += S.c[fe][v][m] * T.psif[f][i][m];
       Um[v] = s;
     }
 #pragma unroll
     for (int m = 0; m < NP; ++m) {
-      Tm += S.aux[el][0][m] * T.psifd[f][i][m];
-      Rm += S.aux[el][1][m] * T.psifd[f][i][m];
+      Tm += S.aux[fe][0][m] * T.psifd[f][i][m];
+      Rm += S.aux[fe][1][m] * T.psifd[f][i][m];
     }
     double b[5];
-    tri_bg<R, K>(t, T, g.layer, z, b);
+    tri_bg<R, K>(t, T, gf.layer, z, b);
     const double rvsm = RAIN ? rho_vs(a, Tm) : 0.0;
     {
       Pt<R, 2, RAIN> pm;
@@ -517,13 +533,13 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
         for (int v = 0; v < NV; ++v) {
           R s = R(0);
 #pragma unroll
-          for (int m = 0; m < NP; ++m) s += S.u.nb.c[el][f][v][m] * T.psif[f2][i2][m];
+          for (int m = 0; m < NP; ++m) s += S.u.nb.c[fe][f][v][m] * T.psif[f2][i2][m];
           Up[v] = s;
         }
 #pragma unroll
         for (int m = 0; m < NP; ++m) {
-          Tp += S.u.nb.aux[el][f][0][m] * T.psifd[f2][i2][m];
-          Rp += S.u.nb.aux[el][f][1][m] * T.psifd[f2][i2][m];
+          Tp += S.u.nb.aux[fe][f][0][m] * T.psifd[f2][i2][m];
+          Rp += S.u.nb.aux[fe][f][1][m] * T.psifd[f2][i2][m];
         }
         double b2[5];
         tri_bg<R, K>(t, T, tri_z(t, e2).layer, z, b2);
@@ -533,10 +549,10 @@ __global__ void __launch_bounds__(256) tri_stage_kernel(KArgs a, TriArgs t, cons
       lp = speed_dir<R, RAIN>(pp, nx, nz);
     }
     const R L = lm >= lp ? lm : lp;
-    const R wgt = (R)(len * idet) * T.wf[i];
+    const R wgt = S.fn[fe][f][2] * T.wf[i];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-      S.ff[el][q][v] = wgt * (R(0.5) * (Fm[v] + Fp[v]) + R(0.5) * L * (Um[v] - Up[v]));
+      S.ff[fe][j][v] = wgt * (R(0.5) * (Fm[v] + Fp[v]) + R(0.5) * L * (Um[v] - Up[v]));
   }
   __syncthreads();
 
