@@ -814,13 +814,20 @@ static void do_gauss_trace(dg_handle* h, const void* U, const double* aT, const 
 }
 
 // artificial diffusion of the state U into the handle's tendency buffer
-static void do_sip(dg_handle* h, const void* U, hipStream_t s) {
+// alpha = false: the stage that produced U already wrote its alpha_K
+static void do_sip(dg_handle* h, const void* U, hipStream_t s, bool alpha = true) {
   KTimer kt(h, DG_K_OTHER, s);
   const LaunchCfg lc = launch_cfg(h);
   if (h->prec == DG_FP64)
-    Launch<double>::sip(h->ka, lc, h->order, h->dim, h->rain, h->nmembers, h->nvert.data(), U, s);
+    Launch<double>::sip(h->ka, lc, h->order, h->dim, h->rain, h->nmembers, h->nvert.data(), U, alpha, s);
   else
-    Launch<float>::sip(h->ka, lc, h->order, h->dim, h->rain, h->nmembers, h->nvert.data(), U, s);
+    Launch<float>::sip(h->ka, lc, h->order, h->dim, h->rain, h->nmembers, h->nvert.data(), U, alpha, s);
+}
+
+// The Q3 hexahedral stage kernel (Lobatto basis) can leave alpha_K of the
+// state it writes for the next stage's diffusion (kSipAlpha).
+static bool stage_writes_alpha(const dg_handle* h) {
+  return h->sip && h->P.basis == DG_BASIS_LOBATTO && h->order == 3 && h->dim == 3;
 }
 
 extern "C" dg_status dg_rhs(dg_handle* h, const void* U, void* dUdt, hipStream_t s) {
@@ -943,8 +950,10 @@ static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t
     // the last stage ends the step and applies the sponge
     const bool last = st == ns - 1;
     const int flags = (last && (step & 3) == 3 ? kRefreshRvs : 0) | (last && h->sponge ? kSponge : 0) |
-                      (h->sip ? kSip : 0);
-    if (h->sip) do_sip(h, in, s);
+                      (h->sip ? kSip : 0) | (stage_writes_alpha(h) ? kSipAlpha : 0);
+    // alpha_K of the stage input: written by the previous stage kernel,
+    // except at the first stage of a call
+    if (h->sip) do_sip(h, in, s, !(stage_writes_alpha(h) && !(first && st == 0)));
     do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], flags, a, b);
     *cur = b;
   }

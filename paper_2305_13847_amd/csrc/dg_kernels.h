@@ -75,6 +75,31 @@ constexpr int kRefreshRvs = 1;   // store a fresh rho_vs(T) evaluation (anchors 
 constexpr int kSponge = 2;       // the stage ends a time step: apply the sponge
 // the diffusive tendency in a.sip_out is added to the right-hand side
 constexpr int kSip = 4;
+// (Q3 stage kernel) the element viscosity alpha_K of the new state is written
+// to a.sip_aK, so the next stage's diffusion need not compute it
+constexpr int kSipAlpha = 8;
+
+// One node's share of the element viscosity of Section 3.5: with quadrature
+// weight w, w |u|^2 and w |u - v_r e_z|^2 (full densities rd, rm, rr, momentum
+// m).  sip_alpha_kernel and the Q3 stage epilogue both call this, and both
+// sum the shares over the element in the same pairwise order, so alpha_K has
+// the same bits whichever kernel formed it.
+template <int D, int RAIN>
+__device__ __forceinline__ void sip_alpha_terms(const KArgs& a, double w, double rd, double rm, double rr,
+                                                const double* m, double& s0, double& s1) {
+  const double irho = 1.0 / (rd + rm + rr);
+  double vr = 0.0;
+  if (RAIN) vr = a.vr_mode == 0 ? a.vr_const : (rr > 0.0 ? a.vr_pref * pow(rr, 0.125) : 0.0);
+  s0 = 0.0;
+  s1 = 0.0;
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    const double ui = m[i] * irho;
+    const double ur = (i == D - 1) ? ui - vr : ui;
+    s0 += w * ui * ui;
+    s1 += w * ur * ur;
+  }
+}
 
 // The sponge at the end of a step (Section 3.6):
 // (rho_m', rho_r', m, E') <- (1 - delta) (rho_m', rho_r', m, E') with the
@@ -413,9 +438,11 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
                                                double c2, double* __restrict__ oT,
                                                double* __restrict__ oS, int flags, int& iters, int& bad,
                                                R* Unew = nullptr, double* Tnew = nullptr,
-                                               double* Snew = nullptr) {
+                                               double* Snew = nullptr, double wq = 0.0,
+                                               double* alpha_terms = nullptr) {
   // (Unew, Tnew, Snew), when given, receive the stored new state and its
-  // stored (T, rho_vs)
+  // stored (T, rho_vs); alpha_terms, when given with kSipAlpha, the node's
+  // shares of the new state's element viscosity (weight wq)
   using V = Vars<D, RAIN>;
   constexpr int NV = V::NV;
   if (MODE == 0) {
@@ -437,6 +464,13 @@ __device__ __forceinline__ void stage_epilogue(const KArgs& a, const double* bg,
   if (flags & kSponge) sponge_point<R, D, RAIN>(a, iz, Un);
 #pragma unroll
   for (int v = 0; v < NV; ++v) st(out, N, v, g, Un[v]);
+  if (alpha_terms && (flags & kSipAlpha)) {
+    double m[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) m[i] = (double)Un[V::M0 + i];
+    sip_alpha_terms<D, RAIN>(a, wq, bg[0] + (double)Un[V::RD], bg[1] + (double)Un[V::RM],
+                             RAIN ? bg[2] + (double)Un[V::RR] : 0.0, m, alpha_terms[0], alpha_terms[1]);
+  }
   if (Unew) {
 #pragma unroll
     for (int v = 0; v < NV; ++v) Unew[v] = Un[v];

@@ -122,16 +122,18 @@ struct Launch {
     });
   }
 
-  // artificial diffusion: alpha_K, vertex means (all members), tendency
+  // artificial diffusion: alpha_K (unless the previous stage wrote it),
+  // vertex means (all members), tendency
   static bool sip(const KArgs& a, LaunchCfg lc, int K, int D, int rain, int nmembers, const long long* nvert,
-                  const void* U, hipStream_t s) {
+                  const void* U, bool alpha, hipStream_t s) {
     return dispatch_shape(K, D, rain, [&](auto k, auto d, auto r) {
       constexpr int K_ = decltype(k)::value, D_ = decltype(d)::value, R_ = decltype(r)::value;
       // one block per work item whatever the persistence setting (the SIP
       // kernels have no item loop)
       const dim3 grid(grid_for_items(a.nitems));
-      hipLaunchKernelGGL((sip_alpha_kernel<R, K_, D_, R_>), grid, dim3(lc.threads), 0, s, a,
-                         (const R*)U);
+      if (alpha)
+        hipLaunchKernelGGL((sip_alpha_kernel<R, K_, D_, R_>), grid, dim3(lc.threads), 0, s, a,
+                           (const R*)U);
       hipLaunchKernelGGL((sip_vertex_kernel<D_>), dim3((unsigned)((a.nvert + 127) / 128)), dim3(128), 0, s, a);
       hipLaunchKernelGGL((sip_kernel<R, K_, D_, R_>), grid, dim3(lc.threads), 0, s, a, (const R*)U);
     });

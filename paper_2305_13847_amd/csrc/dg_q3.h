@@ -318,9 +318,25 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   int iters = 0, bad = 0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) Uq[v] = sU[v][lane];
+  // with kSipAlpha, the new state's element viscosity (Section 3.5) for the
+  // next stage's diffusion: the node shares, then the pairwise sum over the
+  // wavefront in the order of sip_alpha_kernel's tree
+  double at[2] = {0.0, 0.0};
+  const double wq = md.J * a.w[li] * a.w[lj] * a.w[ll];
   stage_epilogue<R, D, RAIN, MODE>(a, bg, iz, g, N, Uq, U0q, Rv, T, rvs, out, dtm, c0, c1, c2, oT, oS, flags,
-                                   iters, bad);
+                                   iters, bad, nullptr, nullptr, nullptr, wq, at);
   if (MODE == 2) record_stats(a, iters, bad);
+  if (MODE == 2 && (flags & kSipAlpha)) {
+#pragma unroll
+    for (int h = 1; h < NP; h <<= 1) {
+      at[0] += __shfl_down(at[0], h);
+      at[1] += __shfl_down(at[1], h);
+    }
+    if (lane == 0) {
+      a.sip_aK[md.eoff + e] = md.sip_pre * sqrt(at[0]);
+      a.sip_aK[a.etot + md.eoff + e] = md.sip_pre * sqrt(at[1]);
+    }
+  }
 }
 
 }  // namespace dgm

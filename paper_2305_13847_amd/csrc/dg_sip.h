@@ -5,7 +5,8 @@
 // carried to a continuous Q1 field by the mean over the elements that share
 // each vertex.  Three kernels per right-hand side:
 //   1. sip_alpha_kernel: alpha_K of every element (two fields), an LDS
-//      reduction over the element's nodes;
+//      reduction over the element's nodes (the Q3 stage kernel forms the same
+//      values for the state it writes, and then this launch is skipped);
 //   2. sip_vertex_kernel: the vertex means (all members in one launch);
 //   3. sip_kernel: the tendency S = -M^{-1} A_h(U, .) at every node, written
 //      in the state layout; the stage kernels add it to the right-hand side.
@@ -50,19 +51,13 @@ sip_alpha_kernel(KArgs a, const R* __restrict__ U) {
     const double rd = a.bg_rd[iz] + (double)ld(U, N, V::RD, g);
     const double rm = a.bg_rm[iz] + (double)ld(U, N, V::RM, g);
     const double rr = RAIN ? a.bg_rr[iz] + (double)ld(U, N, V::RR, g) : 0.0;
-    const double irho = 1.0 / (rd + rm + rr);
     double w = md.J;
 #pragma unroll
     for (int j = 0; j < D; ++j) w *= a.w[idx[j]];
-    double vr = 0.0;
-    if (RAIN) vr = a.vr_mode == 0 ? a.vr_const : (rr > 0.0 ? a.vr_pref * pow(rr, 0.125) : 0.0);
+    double m[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      const double ui = (double)ld(U, N, V::M0 + i, g) * irho;
-      const double ur = (i == D - 1) ? ui - vr : ui;
-      s0 += w * ui * ui;
-      s1 += w * ur * ur;
-    }
+    for (int i = 0; i < D; ++i) m[i] = (double)ld(U, N, V::M0 + i, g);
+    sip_alpha_terms<D, RAIN>(a, w, rd, rm, rr, m, s0, s1);
   }
   sm[0][t] = s0;
   sm[1][t] = s1;

@@ -164,10 +164,14 @@ def test_batch_members_match_single_runs():
         assert np.all(err < 1e-11), err
 
 
+@pytest.mark.parametrize("name", ["rain3d_q2", "rain3d_q3"])
 @pytest.mark.parametrize("scheme", [0, 1])
-def test_with_sponge_and_both_schemes(scheme):
-    # the last stage of every step carries both flags (diffusion, sponge)
-    c = CASES["rain3d_q2"]()
+def test_with_sponge_and_both_schemes(name, scheme):
+    # the last stage of every step carries both flags (diffusion, sponge); on
+    # Q3 hexahedra every stage also forms alpha_K of the (sponged) state it
+    # writes for the next stage
+    c = CASES[name]()
+    print("case", name, scheme, c.digest(), flush=True)
     lib = _lib()
     over = dict(sip_gamma=GAM, sponge_zD=5.0e3, sponge_alpha=0.5)
     dg, U = _gpu(c, lib.DG_FP64, rk=lib.DG_SSPRK43 if scheme == 0 else lib.DG_SSPRK33, **over)
@@ -176,3 +180,43 @@ def test_with_sponge_and_both_schemes(scheme):
     floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
     err = rel_l2(c.mesh, U.cpu().numpy().reshape(c.U.shape), ref, floor=floor)
     assert np.all(err < 1e-11), err
+
+
+def test_batch_of_q3_hexahedra_matches_the_reference():
+    # members of different size: the stage kernel writes alpha_K per member
+    # offset, and the tendency kernel averages it at each member's vertices
+    cases = [_windy(synth.warm_rain_3d(n=(4, 3, 3), order=3, seed=31)),
+             _windy(synth.warm_rain_3d(n=(5, 4, 2), order=3, seed=32), u=6.0)]
+    lib = _lib()
+    dg = lib.for_ensemble(cases, precision=lib.DG_FP64, sip_gamma=GAM)
+    U = torch.cat([torch.tensor(c.U).reshape(c.nvars, -1) for c in cases], dim=1).contiguous().cuda()
+    U = U.reshape(dg.shape)
+    dts = np.array([c.dt for c in cases])
+    dg.rk_step(U, dts, 4)
+    Uh = U.cpu().numpy().reshape(cases[0].nvars, -1)
+    off = 0
+    for c in cases:
+        n = c.mesh.ne * c.mesh.npe
+        got = Uh[:, off:off + n].reshape(c.U.shape)
+        off += n
+        ref, _ = O.Oracle.for_case(c, sip_gamma=GAM).rk(c.U, c.dt, 4)
+        floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
+        err = rel_l2(c.mesh, got, ref, floor=floor)
+        assert np.all(err < 1e-11), err
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-11), (1, 1e-4)])
+def test_rain3d_16x16x8_ten_steps(prec, tol):
+    # the benchmarked diffusion workload's shape (3D warm rain, Q3, walls at
+    # top and bottom) at a size that spans many work items
+    c = _windy(synth.warm_rain_3d(n=(16, 16, 8), order=3, seed=33))
+    print("case rain3d 16x16x8", prec, c.digest(), flush=True)
+    dg, U = _gpu(c, prec, sip_gamma=GAM)
+    dg.rk_step(U, c.dt, 10)
+    torch.cuda.synchronize()
+    assert dg.stats()["status"] == 0
+    ref, _ = O.Oracle.for_case(c, sip_gamma=GAM).rk(c.U, c.dt, 10)
+    floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
+    err = rel_l2(c.mesh, U.double().cpu().numpy().reshape(c.U.shape), ref, floor=floor)
+    print("rel L2 per variable", err)
+    assert np.all(err < tol), err
