@@ -780,11 +780,13 @@ static bool do_split(dg_handle* h, const void* U, const double* guess, double* o
 // the new state (written in mode 2)
 static bool do_rhs(dg_handle* h, int mode, const void* U, const double* aT, const double* aS, void* out,
                    const void* U0, double c0, double c1, double c2, hipStream_t s,
-                   double* oT = nullptr, double* oS = nullptr, int flags = 0, int tin = 0, int tout = 1) {
+                   double* oT = nullptr, double* oS = nullptr, int flags = 0, int tin = 0, int tout = 1,
+                   int rev = 0) {
   KTimer kt(h, DG_K_STAGE, s);
   if (mode == 2) h->splits += h->nnodes;
   const LaunchCfg lc = launch_cfg(h);
   KArgs ka = h->ka;
+  ka.walk_rev = rev;
   if (h->P.basis == DG_BASIS_GAUSS) {
     ka.tr_u_in = h->tr_u[tin];
     ka.tr_a_in = h->tr_a[tin];
@@ -954,7 +956,9 @@ static dg_status rk_one(dg_handle* h, void* U, bool first, int* cur, hipStream_t
     // alpha_K of the stage input: written by the previous stage kernel,
     // except at the first stage of a call
     if (h->sip) do_sip(h, in, s, !(stage_writes_alpha(h) && !(first && st == 0)));
-    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], flags, a, b);
+    // every other stage walks its elements in reverse: it starts on what the
+    // previous stage wrote last, which the last-level cache still holds
+    do_rhs(h, 2, in, aT[a], aS[a], outp, U, c.c0, c.c1, c.c2, s, aT[b], aS[b], flags, a, b, (step * ns + st) & 1);
     *cur = b;
   }
   HIP_TRY(hipGetLastError());

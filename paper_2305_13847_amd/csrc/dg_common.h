@@ -96,6 +96,9 @@ struct KArgs {
   // status words: [0] max iterations, [1] non-converged, [2] invalid, [3] spare,
   // [4..5] split count (64-bit)
   unsigned* stats;
+  // stage kernels: walk the work items from the last one (every other stage,
+  // so a stage starts on the data the previous one wrote last)
+  int walk_rev;
 };
 
 }  // namespace dgm

@@ -49,11 +49,14 @@ __device__ __forceinline__ int elem_stride(const MemberDesc& md, int j) {
 // Consecutive blocks go round-robin to the 8 XCDs; XCD x owns the contiguous
 // item range [x per, (x+1) per), so neighbouring elements share an L2.  With a
 // persistent grid (fewer blocks than items) each block walks its XCD's range
-// with stride gridDim/8.  gridDim.x is always a multiple of 8.
+// with stride gridDim/8.  gridDim.x is always a multiple of 8.  A reversed
+// walk (rev) deals item nitems-1-i where the forward walk deals item i: each
+// XCD then runs its range from the top down.
 struct ItemWalk {
-  int per, g8, x, l, nitems;
-  __device__ __forceinline__ explicit ItemWalk(int n) {
+  int per, g8, x, l, nitems, rev;
+  __device__ __forceinline__ explicit ItemWalk(int n, int reverse = 0) {
     nitems = n;
+    rev = reverse;
     per = (n + 7) >> 3;
     g8 = gridDim.x >> 3;
     x = blockIdx.x & 7;
@@ -64,7 +67,8 @@ struct ItemWalk {
     const int li = l + k * g8;
     if (li >= per) return -1;
     const int it = x * per + li;
-    return it < nitems ? it : -1;
+    if (it >= nitems) return -1;
+    return rev ? nitems - 1 - it : it;
   }
 };
 

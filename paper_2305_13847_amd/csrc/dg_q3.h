@@ -119,7 +119,7 @@ rhs_q3_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   if (threadIdx.x < P1 * P1) sD[threadIdx.x] = (R)a.Dhat[threadIdx.x];
   __syncthreads();   // the only block-wide barrier: the shared D-hat table
 
-  const ItemWalk walk(a.nitems);
+  const ItemWalk walk(a.nitems, a.walk_rev);
   const int it_ = walk.item(0);
   if (it_ < 0) return;
   const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
