@@ -218,12 +218,16 @@ def host_cpu() -> dict:
 
 
 def _weights(case):
-    """Quadrature weight times Jacobian of every node (Lobatto nodes)."""
+    """Quadrature weight times Jacobian of every node (Lobatto nodes, or the
+    Gauss points of the Legendre basis)."""
     m = case.mesh
     k, p1 = m.order, m.order + 1
-    x = synth_mod().lobatto_points(k)
-    Pk = np.polynomial.legendre.legval(x, [0] * k + [1])
-    w = 2.0 / (k * (k + 1) * Pk ** 2)
+    if getattr(m, "basis", "lobatto") == "gauss":
+        w = np.polynomial.legendre.leggauss(p1)[1]
+    else:
+        x = synth_mod().lobatto_points(k)
+        Pk = np.polynomial.legendre.legval(x, [0] * k + [1])
+        w = 2.0 / (k * (k + 1) * Pk ** 2)
     W = np.ones(p1 ** m.dim)
     for a in range(m.dim):
         W *= w[(np.arange(p1 ** m.dim) // p1 ** a) % p1]
@@ -251,9 +255,10 @@ def cpu_baseline(synth, oracle_mod, lib, torch):
     workload (64 x 64 x 32 elements, Q3, 7 variables) after one warm-up
     right-hand side, on all cores (OpenMP over elements); and one step on one
     thread of a 32 x 32 x 32-element column sample (same vertical structure
-    and physics).  The same reference run for ten steps on 16 x 16 x 8
-    elements is the yardstick of the GPU's per-field error in FP32 bulk and
-    FP64.
+    and physics).  The same reference run for ten steps is the yardstick of
+    the GPU's per-field error in FP32 bulk and FP64: on 16 x 16 x 8 elements
+    of the 3D workload, on 8 x 8 x 4 elements of it in the Legendre/Gauss
+    basis, and on the 2D bubble (32 x 16, Q4).
     """
     c = synth.warm_rain_3d()
     o = oracle_mod.Oracle.for_case(c)
@@ -276,19 +281,29 @@ def cpu_baseline(synth, oracle_mod, lib, torch):
         oracle_mod.set_threads(nthreads)
     del o
     # per-field error of the GPU against the reference, ten steps
-    e = synth.warm_rain_3d(n=(16, 16, 8))
-    ref, _ = oracle_mod.Oracle.for_case(e).rk(e.U, e.dt, 10)
-    errs = {}
-    for prec, name in ((lib.DG_FP32_BULK, "fp32_bulk"), (lib.DG_FP64, "fp64")):
-        dg = lib.for_case(e, precision=prec)
-        U = torch.tensor(e.U, dtype=torch.float32 if prec == lib.DG_FP32_BULK else torch.float64,
-                         device="cuda").contiguous()
-        dg.rk_step(U, e.dt, 10)
-        _sync(torch)
-        errs[name] = error_table(U.double().cpu().numpy().reshape(e.U.shape), ref, e)
-        dg.close()
-    errs["variables"] = ["rho_d'", "rho_m'", "rho_r'", "m_x", "m_y", "m_z", "E'"]
-    errs["case"] = "3D warm rain 16x16x8 Q3, 10 SSPRK(4,3) steps, quadrature-weighted relative L2 and max"
+    def field_errors(e, names, label):
+        ref, _ = oracle_mod.Oracle.for_case(e).rk(e.U, e.dt, 10)
+        out = {}
+        for prec, name in ((lib.DG_FP32_BULK, "fp32_bulk"), (lib.DG_FP64, "fp64")):
+            dg = lib.for_case(e, precision=prec)
+            U = torch.tensor(e.U, dtype=torch.float32 if prec == lib.DG_FP32_BULK else torch.float64,
+                             device="cuda").contiguous()
+            dg.rk_step(U, e.dt, 10)
+            _sync(torch)
+            out[name] = error_table(U.double().cpu().numpy().reshape(e.U.shape), ref, e)
+            dg.close()
+        out["variables"] = names
+        out["case"] = label + ", 10 SSPRK(4,3) steps, quadrature-weighted relative L2 and max"
+        return out
+
+    v3 = ["rho_d'", "rho_m'", "rho_r'", "m_x", "m_y", "m_z", "E'"]
+    errs = field_errors(synth.warm_rain_3d(n=(16, 16, 8)), v3, "3D warm rain 16x16x8 Q3")
+    errs["others"] = {
+        "rain3d_q3_gauss": field_errors(synth.warm_rain_3d(n=(8, 8, 4), basis="gauss"), v3,
+                                        "3D warm rain 8x8x4 Q3, Legendre/Gauss basis"),
+        "bubble2d_q4": field_errors(synth.moist_bubble(n=(32, 16)), ["rho_d'", "rho_m'", "m_x", "m_z", "E'"],
+                                    "2D moist bubble 32x16 Q4"),
+    }
     return {"value": dofs_all * 8 / el_all, "unit": "DoF-stage updates/s", "cores": nthreads, "kind": "oracle",
             "sample": "two SSPRK(4,3) steps (8 stages) of the full 3D warm-rain workload (64x64x32 elements, "
                       "Q3, 7 vars, %d DoFs), OpenMP over elements on %d threads, %.1f s"
