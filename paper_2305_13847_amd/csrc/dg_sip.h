@@ -220,8 +220,13 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
         sG[v * NT + t] = dj * acc;
       }
     }
-    // C.
-    for (int task = t; task < epb * NFJ; task += (int)blockDim.x) {
+    // C.  A face point's variables are split over two threads (the first
+    // half and the rest), so the block's 2 EPB NF face points occupy every
+    // thread (each reads k+1 neighbour values per variable).
+    constexpr int VH = (NV + 1) / 2;
+    for (int tv = t; tv < 2 * epb * NFJ; tv += (int)blockDim.x) {
+      const int half = tv >= epb * NFJ;
+      const int task = tv - half * epb * NFJ;
       const int fle = task / NFJ;
       const int r = task - fle * NFJ;
       const int side = r / NF;
@@ -254,6 +259,7 @@ sip_kernel(KArgs a, const R* __restrict__ U) {
       const unsigned gn0 = (unsigned)(md.eoff + en) * NP + nf0;
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
+        if ((v < VH) == (half != 0)) continue;
         R ju = R(0), mg = R(0);
         if (live) {
           R gnb = R(0), unb = R(0), gow = R(0);
