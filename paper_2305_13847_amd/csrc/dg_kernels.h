@@ -587,6 +587,14 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
     const bool at_end = (idx[j] == K) ? (ec.c[j] == md.n[j] - 1) : (ec.c[j] == 0);
     wl[j] = fa[j] && at_end && md.bc[j] == 1;
   }
+  // 2D: the first face pass's neighbour traces are in flight during the
+  // volume term (in 3D the registers they hold would cost a wavefront per
+  // SIMD at some orders)
+  Pair<R, D, RAIN> p0;
+  const int s0 = sp.slot_wave(0);
+  const int J0 = s0 >= 0 ? s0 / sp.swj : 0;
+  if (D == 2 && s0 >= 0)
+    pair_gather_rt<R, K, D, RAIN>(J0, md, item, (s0 - J0 * sp.swj) * sp.wl + sp.lane, sp.pj, U, auxT, auxS, N, p0);
   if (active) {
     volume_dir<R, K, D, RAIN, 0>(md, idx[0], sF, Rv, sD, t);
     volume_dir<R, K, D, RAIN, 1>(md, idx[1], sF + NV * NT, Rv, sD, t);
@@ -601,12 +609,13 @@ __device__ __forceinline__ void rhs_item_pairs(const KArgs& a, int t, int it_, R
     sources<R, D, RAIN>(a, Uq, q, Rv);
   }
   __syncthreads();   // the volume term has read sF
-  // face passes: the neighbour traces are gathered here, not ahead of the
-  // volume term (registers held across it would cost a wavefront per SIMD),
-  // and every pass runs the same code, so the rounding of a face flux does
-  // not depend on the pass (the launch geometry) that computes it
+  // face passes: in 3D the neighbour traces are gathered here, not ahead of
+  // the volume term, and every pass runs the same code, so the rounding of a
+  // face flux does not depend on the pass (the launch geometry) that
+  // computes it
+  if (D == 2 && s0 >= 0) pair_flux_rt<R, K, D, RAIN>(J0, a, md, p0, sF, sU, sL);
 #pragma clang loop unroll(disable)
-  for (int k = 0;; ++k) {
+  for (int k = (D == 2 ? 1 : 0); s0 >= 0; ++k) {
     const int s = sp.slot_wave(k);
     if (s < 0) break;
     const int J = s / sp.swj;
