@@ -293,7 +293,7 @@ rhs_gauss_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ au
   // one work item per block: a loop over items lets the compiler keep
   // loop-invariant values live across the whole body, which about doubles the
   // registers (and halves the occupancy)
-  const int it_ = ItemWalk(a.nitems).item(0);
+  const int it_ = ItemWalk(a.nitems, a.walk_rev).item(0);
   if (it_ < 0) return;
   const Item item = a.items[it_];
   const MemberDesc& md = a.mem[item.member];

@@ -801,7 +801,7 @@ rhs_kernel(KArgs a, const R* __restrict__ U, const double* __restrict__ auxT,
   __shared__ R sU[PAIRS ? V::NV * S::NT : 1];
   __shared__ R sL[PAIRS ? D * S::NT : 1];
   if (threadIdx.x < P1 * P1) sD[threadIdx.x] = (R)a.Dhat[threadIdx.x];
-  const ItemWalk walk(a.nitems);
+  const ItemWalk walk(a.nitems, a.walk_rev);
   const int it_ = walk.item(0);
   if (it_ < 0) return;
   if constexpr (PAIRS)
