@@ -50,8 +50,9 @@ __device__ __forceinline__ int elem_stride(const MemberDesc& md, int j) {
 // item range [x per, (x+1) per), so neighbouring elements share an L2.  With a
 // persistent grid (fewer blocks than items) each block walks its XCD's range
 // with stride gridDim/8.  gridDim.x is always a multiple of 8.  A reversed
-// walk (rev) deals item nitems-1-i where the forward walk deals item i: each
-// XCD then runs its range from the top down.
+// walk (rev) runs each XCD's range from the top down: every XCD keeps its
+// own items (and so what its L2 holds of them) and starts on the ones it
+// wrote last.
 struct ItemWalk {
   int per, g8, x, l, nitems, rev;
   __device__ __forceinline__ explicit ItemWalk(int n, int reverse = 0) {
@@ -66,9 +67,8 @@ struct ItemWalk {
   __device__ __forceinline__ int item(int k) const {
     const int li = l + k * g8;
     if (li >= per) return -1;
-    const int it = x * per + li;
-    if (it >= nitems) return -1;
-    return rev ? nitems - 1 - it : it;
+    const int it = x * per + (rev ? per - 1 - li : li);
+    return it < nitems ? it : -1;
   }
 };
 
