@@ -220,3 +220,24 @@ def test_rain3d_16x16x8_ten_steps(prec, tol):
     err = rel_l2(c.mesh, U.double().cpu().numpy().reshape(c.U.shape), ref, floor=floor)
     print("rel L2 per variable", err)
     assert np.all(err < tol), err
+
+
+def test_q3_launch_shapes_and_graph_agree():
+    # the Q3 hexahedral stage kernel forms alpha_K of the state it writes:
+    # other block widths and a captured graph give the same bits
+    c = CASES["rain3d_q3"]()
+    lib = _lib()
+    outs = []
+    for epb, graph in [(None, False), (2, False), (1, False), (None, True)]:
+        dg, U = _gpu(c, lib.DG_FP32_BULK, sip_gamma=GAM)
+        if epb is not None:
+            dg.set_launch(epb, 0)
+        if graph:
+            dg.rk_step_graph(U, c.dt, 3)
+        else:
+            dg.rk_step(U, c.dt, 3)
+        torch.cuda.synchronize()
+        outs.append(U.cpu().numpy())
+        dg.close()
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
