@@ -198,3 +198,21 @@ def test_mixed_calls_on_one_handle():
     floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref5[-1] ** 2))
     err = rel_l2(c.mesh, U.cpu().numpy().reshape(c.U.shape), ref5, floor=floor)
     assert np.all(err < 1e-11), err
+
+
+def test_state_above_64_mib_with_the_reversed_walk():
+    # a state of more than 64 MiB: every other stage walks its work items in
+    # reverse (each XCD its own range, top down); one SSPRK(4,3) step in FP64
+    # against the reference
+    c = synth.warm_rain_3d(n=(32, 32, 22), order=3, basis=G)
+    assert c.U.nbytes > 64 * 2 ** 20
+    print("case", c.name, c.digest(), flush=True)
+    dg, U = _gpu(c, 0)
+    dg.rk_step(U, c.dt, 1)
+    torch.cuda.synchronize()
+    assert dg.stats()["status"] == 0
+    ref, _ = O.Oracle.for_case(c).rk(c.U, c.dt, 1)
+    floor = 1e-12 * np.sqrt(np.sum(node_weights(c.mesh) * ref[-1] ** 2))
+    err = rel_l2(c.mesh, U.double().cpu().numpy().reshape(c.U.shape), ref, floor=floor)
+    print("rel L2 per variable", err)
+    assert np.all(err < 1e-11), err
